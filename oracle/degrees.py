@@ -1,0 +1,37 @@
+"""Per-vector polynomial degrees (paper Sec. 2.3 last paragraph; Sec. 4.2).
+
+Oracle module (test infrastructure only).
+
+PARITY UNPINNED: the paper says each vector is filtered with a degree "just
+high enough" to converge within the tolerance, with the initial degree 20 and
+a cap of 36 in its experiments, but gives no formula.  The reading used here:
+a column whose residual is r and whose Ritz value has convergence ratio
+1/|rho| needs about ln(r/tol)/ln|rho| more filter steps, so
+m_a = ceil(ln(r_a/tol) / ln|rho(theta_a)|) + margin, clamped to
+[min_deg, max_deg], with a margin of 2 degrees (the convergence-ratio model
+predicts only the decay rate; aimed exactly at tol the residuals settle at
+about tol and then need many one-degree passes to cross it);
+|rho| = 1 (a Ritz value inside the damped interval) gives max_deg; a residual
+already below tol gives min_deg.  Only the clamp range and the ascending order
+used by the filter are fixed by the paper.
+"""
+import math
+
+import numpy as np
+
+from .chebyshev import rho_abs
+
+
+def optimised_degrees(theta, resid, tol, c, e, min_deg, max_deg, margin=2):
+    out = np.empty(len(theta), dtype=np.int64)
+    for a, (th, r) in enumerate(zip(theta, resid)):
+        if r <= tol:
+            out[a] = min_deg
+            continue
+        rho = rho_abs(float(th), c, e)
+        if rho <= 1.0:
+            out[a] = max_deg
+            continue
+        d = math.ceil(math.log(r / tol) / math.log(rho)) + margin
+        out[a] = min(max(d, min_deg), max_deg)
+    return out

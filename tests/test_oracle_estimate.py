@@ -1,0 +1,80 @@
+"""Pins of oracle/estimate.py (eq:simple-est, eq:full-est, Alg. 3)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimate as est
+from oracle import solver
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+PHI = (1 + math.sqrt(5)) / 2
+
+
+def test_hand_evaluated_simple_estimate():
+    # c = 0, e = 1, gamma = -2: |rho_1| = 2 + sqrt(3); (2+sqrt3)^5 = 2*C_5(2) - (2-sqrt3)^5
+    v = est.cond_estimate(-2.0, 5, 5, -2.0, 0.0, 1.0)
+    assert v == pytest.approx(2 * 362 - (2 - math.sqrt(3)) ** 5, rel=1e-13)
+
+
+def test_hand_evaluated_full_estimate():
+    # theta_{k+1} = -1.5 -> |rho| = phi^2; m_{k+1} = 3, m_l = 5, gamma = -2:
+    # est = phi^6 (2+sqrt3)^2 = (9 + 4 sqrt5)(7 + 4 sqrt3)
+    v = est.cond_estimate(-1.5, 3, 5, -2.0, 0.0, 1.0)
+    assert v == pytest.approx((9 + 4 * math.sqrt(5)) * (7 + 4 * math.sqrt(3)), rel=1e-13)
+    assert PHI**6 == pytest.approx(9 + 4 * math.sqrt(5), rel=1e-14)
+
+
+@pytest.mark.parametrize("m_next,m_max", [(1, 20), (20, 20), (7, 36)])
+def test_full_reduces_to_simple_without_locking(m_next, m_max):
+    # eq:full-est with theta_{k+1} = lambda_1 (nothing locked) is eq:simple-est with m -> m_l
+    c, e, g = 0.063, 0.936, -0.999
+    full = est.cond_estimate(g, m_next, m_max, g, c, e)
+    simple = est.cond_estimate(g, m_max, m_max, g, c, e)
+    assert full == pytest.approx(simple, rel=1e-12)
+
+
+def test_no_opt_reduces_to_single_ratio():
+    # fixed degree: the estimate is |rho_{k+1}|^m (Sec. 4.2)
+    c, e, g, th, m = 0.0, 1.0, -2.0, -1.5, 20
+    assert est.cond_estimate(th, m, m, g, c, e) == pytest.approx(PHI ** (2 * m), rel=1e-12)
+
+
+def test_locking_never_raises_estimate():
+    c, e, g = 0.0, 1.0, -2.0
+    top = est.cond_estimate(g, 36, 36, g, c, e)
+    for th in np.linspace(-2.0, -1.0, 11):
+        for mn in [1, 10, 36]:
+            assert est.cond_estimate(float(th), mn, 36, g, c, e) <= top * (1 + 1e-12)
+
+
+def test_overflow_is_infinite_not_error():
+    assert est.cond_estimate(-1e6, 200, 400, -1e6, 0.0, 1.0) == float("inf")
+    assert est.log_cond_estimate(-1e6, 200, 400, -1e6, 0.0, 1.0) > 709
+
+
+def test_variant_thresholds_from_paper():
+    hi, lo = GOLD["alg3_thresholds"]["hi"], GOLD["alg3_thresholds"]["lo"]
+    assert (est.EST_HI, est.EST_LO) == (hi, lo)
+    assert est.select_variant(1.0000001e8) == "shifted"
+    assert est.select_variant(1e8) == "chol2"
+    assert est.select_variant(20.0) == "chol2"
+    assert est.select_variant(19.999) == "chol1"
+    assert est.select_variant(float("inf")) == "shifted"
+
+
+@pytest.mark.parametrize("deg_opt", [False, True])
+def test_estimate_bounds_exact_condition_number(deg_opt):
+    """Empirical property reported in Sec. 4.2: the estimate stays above the
+    exact kappa_2 (by SVD) of [Y, filtered] at every iteration."""
+    N, nev, nex = 400, 16, 10
+    H, lam = synth.planted_numpy(N, "uniform", 21)
+    V0 = synth.start_block(N, nev + nex, 22)
+    r = solver.chase_solve(H, nev, nex, 20, 1e-10, V0=V0, deg_opt=deg_opt,
+                           bounds=(lam[0], lam[nev + nex - 1], lam[-1]), exact_cond=True)
+    assert r.converged == nev
+    for rec in r.log:
+        assert rec["cond_est"] >= rec["cond_exact"], rec
