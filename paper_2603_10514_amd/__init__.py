@@ -1,0 +1,359 @@
+"""Python binding of libchase.so, the gfx950 library behind include/chase.h.
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device buffers are torch tensors on the GPU (column-major: stride(0) == 1);
+they are passed as raw pointers together with torch's current stream, so the
+library's work is ordered after torch's.  Importing this package raises if
+libchase.so has not been built (python -m paper_2603_10514_amd.build).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchase.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libchase.so is not built; run `python -m paper_2603_10514_amd.build` "
+                      "(the solver has no fallback path)")
+lib = ctypes.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------- enums --------
+CHASE_OK, CHASE_NOT_CONVERGED = 0, 1
+CHASE_EINVAL, CHASE_ENOMEM, CHASE_EDEVICE, CHASE_EINTERNAL, CHASE_EBUSY = -1, -2, -3, -4, -5
+REAL64, COMPLEX128 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+QR_AUTO, QR_CHOL1, QR_CHOL2, QR_SHIFTED, QR_HOUSEHOLDER = 0, 1, 2, 3, 4
+QR_NAMES = {1: "chol1", 2: "chol2", 3: "shifted", 4: "householder"}
+QR_CODES = {v: k for k, v in QR_NAMES.items()}
+
+
+class ChaseIterLog(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("locked", ctypes.c_int32),
+                ("newly_locked", ctypes.c_int32), ("qr_variant", ctypes.c_int32),
+                ("chol_failed", ctypes.c_int32), ("filter_prec", ctypes.c_int32),
+                ("deg_min", ctypes.c_int32), ("deg_max", ctypes.c_int32),
+                ("matvecs", ctypes.c_int64), ("cond_est", ctypes.c_double),
+                ("c", ctypes.c_double), ("e", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("lam1", ctypes.c_double), ("t_filter", ctypes.c_double),
+                ("t_qr", ctypes.c_double), ("t_rr", ctypes.c_double),
+                ("t_resid", ctypes.c_double)]
+
+
+LOG_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(ChaseIterLog), ctypes.c_void_p)
+
+
+class ChaseOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("dtype", ctypes.c_int),
+                ("precision", ctypes.c_int), ("deg_opt", ctypes.c_int32),
+                ("min_deg", ctypes.c_int32), ("max_deg", ctypes.c_int32),
+                ("deg_margin", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("qr_policy", ctypes.c_int), ("est_hi", ctypes.c_double),
+                ("est_lo", ctypes.c_double), ("have_bounds", ctypes.c_int32),
+                ("lambda_1", ctypes.c_double), ("lambda_l", ctypes.c_double),
+                ("lambda_max", ctypes.c_double), ("warm_start", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("lanczos_steps", ctypes.c_int32),
+                ("lanczos_v0", ctypes.c_void_p), ("inject_chol_fail_iter", ctypes.c_int32),
+                ("mixed_switch", ctypes.c_double), ("stream", ctypes.c_void_p),
+                ("log_cb", LOG_CB), ("log_user", ctypes.c_void_p)]
+
+
+class ChaseInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("matvecs", ctypes.c_int64), ("filter_launches", ctypes.c_int32),
+                ("filter_fp32_iters", ctypes.c_int32), ("t_total", ctypes.c_double),
+                ("t_filter", ctypes.c_double), ("t_qr", ctypes.c_double),
+                ("t_rr", ctypes.c_double), ("t_resid", ctypes.c_double),
+                ("t_lanczos", ctypes.c_double), ("lambda_1", ctypes.c_double),
+                ("lambda_l", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_d = ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("chase_opts_default", None, [ctypes.POINTER(ChaseOpts)])
+_sig("chase_solve", ctypes.c_int, [_p, _i64, _i64, _i32, _i32, _i32, _d, ctypes.POINTER(ChaseOpts),
+                                   _dp, _p, _i64, _dp, ctypes.POINTER(ChaseInfo)])
+_sig("chase_workspace_bytes", ctypes.c_size_t, [_i64, _i32, _i32, ctypes.c_int, ctypes.c_int])
+_sig("chase_handle_create", ctypes.c_int, [_i64, _i32, _i32, ctypes.POINTER(ChaseOpts),
+                                           ctypes.POINTER(_p)])
+_sig("chase_solve_async", ctypes.c_int, [_p, _p, _i64, _i64, _i32, _i32, _i32, _d,
+                                         ctypes.POINTER(ChaseOpts), _dp, _p, _i64, _dp,
+                                         ctypes.POINTER(ChaseInfo)])
+_sig("chase_handle_query", ctypes.c_int, [_p])
+_sig("chase_handle_wait", ctypes.c_int, [_p])
+_sig("chase_handle_destroy", None, [_p])
+_sig("chase_filter", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _p, _i64, _i64, _p, _i64, _i32,
+                                    _ip, _d, _d, _d, _p, _i64, _p])
+_sig("chase_log_cond_estimate", _d, [_d, _i32, _i32, _d, _d, _d])
+_sig("chase_select_qr", ctypes.c_int, [_d, _d, _d])
+_sig("chase_degrees", None, [_dp, _dp, _i32, _d, _d, _d, _i32, _i32, _i32, _ip])
+_sig("chase_qr_factor", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _i32, ctypes.c_int, _ip, _p])
+_sig("chase_rayleigh_ritz", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i64, _i32, _dp,
+                                           _p, _i64, _p, _i64, _p])
+_sig("chase_residuals", ctypes.c_int, [ctypes.c_int, _p, _i64, _p, _i64, _i64, _i32, _dp, _dp, _p])
+_sig("chase_lanczos", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i32, _i32, _dp, _dp, _dp,
+                                     _p])
+_sig("chase_strerror", ctypes.c_char_p, [ctypes.c_int])
+_sig("chase_last_error", ctypes.c_char_p, [])
+
+
+class ChaseError(RuntimeError):
+    def __init__(self, status, where):
+        msg = "%s: %s (%s)" % (where, lib.chase_strerror(status).decode(),
+                               lib.chase_last_error().decode())
+        super().__init__(msg)
+        self.status = status
+
+
+def _check(status, where, allow=(CHASE_OK,)):
+    if status not in allow:
+        raise ChaseError(status, where)
+    return status
+
+
+# ------------------------------------------------------ marshalling -------
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return REAL64
+    if t.dtype == torch.complex128:
+        return COMPLEX128
+    raise TypeError("matrices must be float64 or complex128, got %s" % (t.dtype,))
+
+
+def _colmajor(t, name, allow_symmetric_rowmajor=False):
+    """(pointer, leading dimension) of a column-major device matrix."""
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if t.dim() == 1:
+        return t.data_ptr(), max(1, t.shape[0])
+    if t.stride(0) == 1:
+        return t.data_ptr(), max(t.stride(1), t.shape[0])
+    if allow_symmetric_rowmajor and t.is_contiguous() and t.shape[0] == t.shape[1]:
+        return t.data_ptr(), t.shape[0]
+    raise ValueError("%s must be column-major (stride(0) == 1)" % name)
+
+
+def _hermitian_ptr(H):
+    import torch
+    # a row-major real symmetric matrix is its own column-major storage
+    return _colmajor(H, "H", allow_symmetric_rowmajor=(H.dtype == torch.float64))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def colmajor_empty(rows, cols, dtype, device):
+    """An uninitialised column-major rows x cols device tensor."""
+    import torch
+    return torch.empty((cols, rows), dtype=dtype, device=device).T
+
+
+def opts_default(**kw):
+    o = ChaseOpts()
+    lib.chase_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "qr_policy" and isinstance(v, str):
+            v = QR_AUTO if v == "auto" else QR_CODES[v]
+        setattr(o, k, v)
+    return o
+
+
+def _info_dict(info):
+    return {f: getattr(info, f) for f, _ in ChaseInfo._fields_}
+
+
+def _log_dict(rec):
+    d = {f: getattr(rec, f) for f, _ in ChaseIterLog._fields_}
+    d["variant"] = QR_NAMES.get(d["qr_variant"], "?")
+    return d
+
+
+# ----------------------------------------------------------- solve --------
+def chase_solve(H, nev, nex, degree=20, tol=1e-10, evecs=None, opts=None, stream=None, **kw):
+    """Alg. 1 on the device matrix H.  Returns a dict with status, evals and
+    resid (numpy), evecs (the N x (nev+nex) column-major device tensor), info
+    and the per-iteration log.  Keyword arguments override chase_opts fields;
+    pass evecs with warm_start=1 to start from a given block."""
+    import torch
+    N = H.shape[0]
+    L = nev + nex
+    o = opts if opts is not None else opts_default()
+    for k, v in kw.items():
+        if k == "qr_policy" and isinstance(v, str):
+            v = QR_AUTO if v == "auto" else QR_CODES[v]
+        setattr(o, k, v)
+    o.dtype = _dtype_code(H)
+    hp, ldh = _hermitian_ptr(H)
+    if evecs is None:
+        evecs = colmajor_empty(N, L, H.dtype, H.device)
+    vp, ldv = _colmajor(evecs, "evecs")
+    logs = []
+
+    def _cb(rec_ptr, user):
+        logs.append(_log_dict(rec_ptr.contents))
+
+    cb = LOG_CB(_cb)
+    o.log_cb = cb
+    o.stream = _stream_ptr(stream).value
+    evals = np.zeros(nev)
+    resid = np.zeros(nev)
+    info = ChaseInfo()
+    st = lib.chase_solve(hp, N, ldh, nev, nex, degree, tol, ctypes.byref(o),
+                         evals.ctypes.data_as(_dp), vp, ldv, resid.ctypes.data_as(_dp),
+                         ctypes.byref(info))
+    o.log_cb = LOG_CB()
+    _check(st, "chase_solve", (CHASE_OK, CHASE_NOT_CONVERGED))
+    return dict(status=st, evals=evals, resid=resid, evecs=evecs, info=_info_dict(info), log=logs)
+
+
+def chase_workspace_bytes(N, nev, nex, dtype=REAL64, precision=PREC_FP64):
+    return int(lib.chase_workspace_bytes(N, nev, nex, dtype, precision))
+
+
+# ------------------------------------------------------- step calls -------
+def chase_filter(H, V, degrees, c, e, gamma, out=None, precision=PREC_FP64, stream=None):
+    """Filter every column of V with its own degree (ascending)."""
+    N = H.shape[0]
+    deg = np.ascontiguousarray(np.asarray(degrees, dtype=np.int32))
+    hp, ldh = _hermitian_ptr(H)
+    vp, ldv = _colmajor(V, "V")
+    if out is None:
+        out = colmajor_empty(N, V.shape[1], H.dtype, H.device)
+    op, ldo = _colmajor(out, "out")
+    st = lib.chase_filter(_dtype_code(H), precision, hp, N, ldh, vp, ldv, int(deg.size),
+                          deg.ctypes.data_as(_ip), c, e, gamma, op, ldo, _stream_ptr(stream))
+    _check(st, "chase_filter")
+    return out
+
+
+def chase_log_cond_estimate(theta_next, m_next, m_max, lam1, c, e):
+    return float(lib.chase_log_cond_estimate(theta_next, m_next, m_max, lam1, c, e))
+
+
+def chase_select_qr(est, hi=1e8, lo=20.0):
+    return QR_NAMES[int(lib.chase_select_qr(est, hi, lo))]
+
+
+def chase_degrees(theta, resid, tol, c, e, min_deg=1, max_deg=36, margin=2):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    r = np.ascontiguousarray(resid, dtype=np.float64)
+    out = np.zeros(th.size, dtype=np.int32)
+    lib.chase_degrees(th.ctypes.data_as(_dp), r.ctypes.data_as(_dp), th.size, tol, c, e,
+                      min_deg, max_deg, margin, out.ctypes.data_as(_ip))
+    return out
+
+
+def chase_qr_factor(X, variant, stream=None):
+    """Orthonormalise X in place with one variant; returns chol_failed."""
+    if isinstance(variant, str):
+        variant = QR_CODES[variant]
+    xp, ldx = _colmajor(X, "X")
+    failed = ctypes.c_int32(0)
+    st = lib.chase_qr_factor(_dtype_code(X), xp, X.shape[0], ldx, X.shape[1], variant,
+                             ctypes.byref(failed), _stream_ptr(stream))
+    _check(st, "chase_qr_factor")
+    return bool(failed.value)
+
+
+def chase_rayleigh_ritz(H, Q, stream=None):
+    N, n = Q.shape
+    hp, ldh = _hermitian_ptr(H)
+    qp, ldq = _colmajor(Q, "Q")
+    V = colmajor_empty(N, n, H.dtype, H.device)
+    HV = colmajor_empty(N, n, H.dtype, H.device)
+    ritz = np.zeros(n)
+    st = lib.chase_rayleigh_ritz(_dtype_code(H), hp, N, ldh, qp, ldq, n, ritz.ctypes.data_as(_dp),
+                                 V.data_ptr(), N, HV.data_ptr(), N, _stream_ptr(stream))
+    _check(st, "chase_rayleigh_ritz")
+    return ritz, V, HV
+
+
+def chase_residuals(HV, V, ritz, stream=None):
+    N, n = V.shape
+    hp, ldh = _colmajor(HV, "HV")
+    vp, ldv = _colmajor(V, "V")
+    th = np.ascontiguousarray(ritz, dtype=np.float64)
+    out = np.zeros(n)
+    st = lib.chase_residuals(_dtype_code(V), hp, ldh, vp, ldv, N, n, th.ctypes.data_as(_dp),
+                             out.ctypes.data_as(_dp), _stream_ptr(stream))
+    _check(st, "chase_residuals")
+    return out
+
+
+def chase_lanczos(H, v0, steps, nsearch, stream=None):
+    N = H.shape[0]
+    hp, ldh = _hermitian_ptr(H)
+    a = np.zeros(steps)
+    b = np.zeros(steps)
+    bounds = np.zeros(3)
+    st = lib.chase_lanczos(_dtype_code(H), hp, N, ldh, v0.data_ptr(), steps, nsearch,
+                           a.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
+                           bounds.ctypes.data_as(_dp), _stream_ptr(stream))
+    _check(st, "chase_lanczos")
+    k = min(steps, N)
+    return a[:k], b[:k], tuple(bounds)
+
+
+# ------------------------------------------------------ async handles -----
+class Handle:
+    """Owns a chase_handle: its own stream, workspace and worker thread."""
+
+    def __init__(self, N_max, nev_max, nex_max, opts=None):
+        o = opts if opts is not None else opts_default()
+        h = ctypes.c_void_p()
+        _check(lib.chase_handle_create(N_max, nev_max, nex_max, ctypes.byref(o),
+                                       ctypes.byref(h)), "chase_handle_create")
+        self._h = h
+        self._keep = None
+
+    def solve_async(self, H, nev, nex, degree, tol, evecs, opts):
+        N = H.shape[0]
+        hp, ldh = _hermitian_ptr(H)
+        vp, ldv = _colmajor(evecs, "evecs")
+        opts.dtype = _dtype_code(H)
+        opts.log_cb = LOG_CB()
+        opts.stream = None
+        evals = np.zeros(nev)
+        resid = np.zeros(nev)
+        info = ChaseInfo()
+        self._keep = (H, evecs, opts, evals, resid, info)
+        _check(lib.chase_solve_async(self._h, hp, N, ldh, nev, nex, degree, tol, ctypes.byref(opts),
+                                     evals.ctypes.data_as(_dp), vp, ldv,
+                                     resid.ctypes.data_as(_dp), ctypes.byref(info)),
+               "chase_solve_async")
+        return evals, resid, info
+
+    def query(self):
+        return int(lib.chase_handle_query(self._h))
+
+    def wait(self):
+        return int(lib.chase_handle_wait(self._h))
+
+    def close(self):
+        if self._h:
+            lib.chase_handle_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,268 @@
+// One MFMA GEMM core for every dense contraction of the solver:
+//   C(M x N) = op(A) B, reduction over K, with a fused epilogue.
+//
+//  * A is read either "K-contiguous" (AT = true: A(i,k) at A[i*lda + k], i.e.
+//    the memory holds A^T column-major; with CONJA the element is conjugated)
+//    or "M-contiguous" (AT = false: A(i,k) at A[k*lda + i], plain column-major).
+//    The filter reads H this way with A(i,k) = conj(H[k + i*ldh]) = H(i,k) for a
+//    Hermitian H, so both operands stream along contiguous columns.
+//  * B is column-major K x N: B(k,j) at B[(col0 + j)*ldb + k].
+//  * Complex products use four real MFMAs per block of 16x16 outputs
+//    (re = ar br - ai bi, im = ar bi + ai br).
+//  * MFMA: v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32 (FP32); both
+//    take A(i = lane%16, k = lane/16) and B(k = lane/16, j = lane%16).  The
+//    four results of a lane are D(i, j = lane%16) with i = 4*(lane/16) + r for
+//    FP32 but i = lane/16 + 4*r for FP64 (r = 0..3; measured on gfx950).
+//  * 256 threads = 4 waves in a 2 x 2 arrangement; LDS double-buffered tiles
+//    with a register prefetch of the next K chunk; tiles stored [k][i] with one
+//    element of padding so that the transposing stores are conflict-free.
+//  * Block -> tile mapping is XCD aware: consecutive hardware block ids go
+//    round-robin to the 8 XCDs, so each XCD is handed a contiguous range of
+//    logical tiles (N-tile fastest) and the blocks sharing an A row panel run
+//    on the same XCD and reuse it from that XCD's L2.
+//
+// Epilogues:
+//  EPI_AXPBY   C = alpha * acc + beta * C (beta == 0: C not read); with K
+//              splits, split s writes C + s * split_stride.
+//  EPI_FILTER  one step of the sigma-scaled Chebyshev recurrence (Alg. 4):
+//              out = alpha * (acc - shift * Xcur) + beta * Xprev, where Xcur is
+//              B itself (K == M); column j goes to Ofinal when deg[j] == step
+//              (its last step, Sec. 2.3) and to Onext otherwise.
+#pragma once
+#include "common.hpp"
+
+namespace chase {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4v acc;
+  __device__ static __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+  __device__ static __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  typedef f4v acc;
+  __device__ static __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+  __device__ static __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+enum { EPI_AXPBY = 0, EPI_FILTER = 1 };
+
+struct GemmArgs {
+  const void *A; int64_t lda;
+  const void *B; int64_t ldb;
+  int M, N, K;
+  int col0;              // first global column of B (and of the filter buffers)
+  int ccol0;             // first global column of C (EPI_AXPBY)
+  int tri;               // skip blocks strictly below the diagonal of C
+  int kcap;              // B upper triangular: block column n uses k < col0 + n0 + BN
+  int k_per_split;       // K range of one split (multiple of BK); grid.y = #splits
+  int64_t split_stride;  // elements between the outputs of two splits
+  void *C; int64_t ldc;  // EPI_AXPBY
+  double alpha, beta;
+  double shift;          // EPI_FILTER
+  const void *Xprev; int64_t ldp;
+  void *Onext; int64_t ldn;
+  void *Ofinal; int64_t ldf;
+  const int *deg; int step;
+  const int *flag;       // non-null and *flag != 0: the launch does nothing
+};
+
+template <typename T, bool CPLX, bool AT, bool CONJA, int BM, int BN, int BK, int WM, int WN,
+          int EPI, typename FT>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
+  typedef typename Elem<T, CPLX>::type E;
+  typedef typename Mfma<T>::acc Acc;
+  constexpr int NT = 256;
+  constexpr int NWM = BM / WM;
+  static_assert(NWM * (BN / WN) == 4, "four waves per block");
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int NP = CPLX ? 2 : 1;
+  constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
+  static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile / thread mismatch");
+
+  __shared__ T As[2][NP][BK][BM + 1];
+  __shared__ T Bs[2][NP][BK][BN + 1];
+
+  if (p.flag != nullptr && *p.flag != 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % NWM, wn = wave / NWM;
+  const int nbm = (p.M + BM - 1) / BM, nbn = (p.N + BN - 1) / BN;
+  const int nb = nbm * nbn;
+  // XCD-aware remap of the hardware block id (bijective on [0, nb)).
+  const int hb = blockIdx.x;
+  const int xcd = hb & 7, q = hb >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  const int logical = xcd * per + (xcd < rem ? xcd : rem) + q;
+  const int bm = logical / nbn, bn = logical % nbn;
+  const int m0 = bm * BM, n0 = bn * BN;
+  if (p.tri && m0 > n0 + BN - 1) return;
+
+  int kbeg = blockIdx.y * p.k_per_split;
+  int kend = kbeg + p.k_per_split;
+  if (kend > p.K) kend = p.K;
+  if (p.kcap) {
+    int cap = p.col0 + n0 + BN;
+    if (kend > cap) kend = cap;
+  }
+
+  const E *Ag = reinterpret_cast<const E *>(p.A);
+  const E *Bg = reinterpret_cast<const E *>(p.B);
+
+  Acc accR[FM][FN];
+  Acc accI[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+
+  E ra[AE], rb[BE];
+  const E zero = make_elem<E>(0.0, 0.0);
+
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + e * NT;
+      int i, k;
+      if (AT) { k = idx % BK; i = idx / BK; } else { i = idx % BM; k = idx / BM; }
+      const int gi = m0 + i, gk = k0 + k;
+      if (gi < p.M && gk < kend)
+        ra[e] = AT ? Ag[(int64_t)gi * p.lda + gk] : Ag[(int64_t)gk * p.lda + gi];
+      else
+        ra[e] = zero;
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + e * NT;
+      const int k = idx % BK, j = idx / BK;
+      const int gj = n0 + j, gk = k0 + k;
+      if (gj < p.N && gk < kend)
+        rb[e] = Bg[(int64_t)(p.col0 + gj) * p.ldb + gk];
+      else
+        rb[e] = zero;
+    }
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int idx = tid + e * NT;
+      int i, k;
+      if (AT) { k = idx % BK; i = idx / BK; } else { i = idx % BM; k = idx / BM; }
+      As[buf][0][k][i] = re_of(ra[e]);
+      if constexpr (CPLX) As[buf][NP - 1][k][i] = CONJA ? -im_of(ra[e]) : im_of(ra[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int idx = tid + e * NT;
+      const int k = idx % BK, j = idx / BK;
+      Bs[buf][0][k][j] = re_of(rb[e]);
+      if constexpr (CPLX) Bs[buf][NP - 1][k][j] = im_of(rb[e]);
+    }
+  };
+
+  const int lr = lane & 15, lk = lane >> 4;
+  int buf = 0;
+  if (kbeg < kend) {
+    load_tiles(kbeg);
+    store_tiles(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = (k0 + BK) < kend;
+    if (more) load_tiles(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T ar[FM], ai[FM], br[FN], bi[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        ar[a] = As[buf][0][kk + lk][wm * WM + a * 16 + lr];
+        if constexpr (CPLX) ai[a] = As[buf][NP - 1][kk + lk][wm * WM + a * 16 + lr];
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        br[b] = Bs[buf][0][kk + lk][wn * WN + b * 16 + lr];
+        if constexpr (CPLX) bi[b] = Bs[buf][NP - 1][kk + lk][wn * WN + b * 16 + lr];
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          accR[a][b] = Mfma<T>::op(ar[a], br[b], accR[a][b]);
+          if constexpr (CPLX) {
+            accR[a][b] = Mfma<T>::op(-ai[a], bi[b], accR[a][b]);
+            accI[a][b] = Mfma<T>::op(ar[a], bi[b], accI[a][b]);
+            accI[a][b] = Mfma<T>::op(ai[a], br[b], accI[a][b]);
+          }
+        }
+      }
+    }
+    if (more) store_tiles(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // ---------------------------------------------------------- epilogue --
+  const T alpha = (T)p.alpha, beta = (T)p.beta;
+#pragma unroll
+  for (int b = 0; b < FN; ++b) {
+    const int j = n0 + wn * WN + b * 16 + lr;
+    if (j >= p.N) continue;
+    const int jg = p.col0 + j;
+    if (EPI == EPI_AXPBY) {
+      E *Cg = reinterpret_cast<E *>(p.C) + (int64_t)blockIdx.y * p.split_stride +
+              (int64_t)(p.ccol0 + j) * p.ldc;
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = m0 + wm * WM + a * 16 + Mfma<T>::row(lk, r);
+          if (i >= p.M) continue;
+          T vr = alpha * accR[a][b][r], vi = alpha * accI[a][b][r];
+          if (p.beta != 0.0) {
+            const E c = Cg[i];
+            vr += beta * re_of(c);
+            vi += beta * im_of(c);
+          }
+          Cg[i] = make_elem<E>(vr, vi);
+        }
+    } else {
+      typedef typename Elem<FT, CPLX>::type EF;
+      const bool fin = p.deg[jg] == p.step;
+      const T shift = (T)p.shift;
+      const E *Xc = Bg + (int64_t)jg * p.ldb;
+      const E *Xp = reinterpret_cast<const E *>(p.Xprev) + (int64_t)jg * p.ldp;
+      E *On = reinterpret_cast<E *>(p.Onext) + (int64_t)jg * p.ldn;
+      EF *Of = reinterpret_cast<EF *>(p.Ofinal) + (int64_t)jg * p.ldf;
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = m0 + wm * WM + a * 16 + Mfma<T>::row(lk, r);
+          if (i >= p.M) continue;
+          const E x = Xc[i];
+          T vr = alpha * (accR[a][b][r] - shift * re_of(x));
+          T vi = alpha * (accI[a][b][r] - shift * im_of(x));
+          if (p.beta != 0.0) {
+            const E xp = Xp[i];
+            vr += beta * re_of(xp);
+            vi += beta * im_of(xp);
+          }
+          if (fin)
+            Of[i] = make_elem<EF>((double)vr, (double)vi);
+          else
+            On[i] = make_elem<E>(vr, vi);
+        }
+    }
+  }
+}
+
+}  // namespace chase

@@ -1,0 +1,430 @@
+// gfx950 kernels of the solver other than the GEMM core, the GEMM
+// instantiations, and their launchers.
+#include <cmath>
+
+#include "gemm.hpp"
+#include "kernels.hpp"
+
+namespace chase {
+
+// ------------------------------------------------------- scalar helpers --
+template <typename E> struct Num;
+template <> struct Num<double> {
+  __device__ static double zero() { return 0.0; }
+  __device__ static double mul(double a, double b) { return a * b; }
+  __device__ static double cj(double a) { return a; }
+  __device__ static double abs2(double a) { return a * a; }
+  __device__ static double re(double a) { return a; }
+  __device__ static double im(double) { return 0.0; }
+  __device__ static double real(double r) { return r; }
+  __device__ static double scale(double a, double s) { return a * s; }
+};
+template <> struct Num<double2> {
+  __device__ static double2 zero() { return make_double2(0.0, 0.0); }
+  __device__ static double2 mul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  }
+  __device__ static double2 cj(double2 a) { return make_double2(a.x, -a.y); }
+  __device__ static double abs2(double2 a) { return a.x * a.x + a.y * a.y; }
+  __device__ static double re(double2 a) { return a.x; }
+  __device__ static double im(double2 a) { return a.y; }
+  __device__ static double2 real(double r) { return make_double2(r, 0.0); }
+  __device__ static double2 scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+};
+__device__ __forceinline__ double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 operator-(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 operator-(double2 a) { return make_double2(-a.x, -a.y); }
+
+// Deterministic block reduction of one double over 256 threads.
+__device__ __forceinline__ double block_sum256(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// -------------------------------------------------- Hermitian reduction --
+template <typename E>
+__global__ void k_reduce_herm(const E *P, int nsplit, int64_t sstride, int64_t ldp, int n, E *G,
+                              int64_t ldg, int average) {
+  const int i = blockIdx.x * 16 + threadIdx.x;
+  const int j = blockIdx.y * 16 + threadIdx.y;
+  if (i >= n || j >= n || i > j) return;
+  E s = Num<E>::zero(), t = Num<E>::zero();
+  for (int q = 0; q < nsplit; ++q) {
+    s = s + P[q * sstride + (int64_t)j * ldp + i];
+    if (average) t = t + P[q * sstride + (int64_t)i * ldp + j];
+  }
+  if (average) s = Num<E>::scale(s + Num<E>::cj(t), 0.5);
+  if (i == j) s = Num<E>::real(Num<E>::re(s));
+  G[(int64_t)j * ldg + i] = s;
+  G[(int64_t)i * ldg + j] = Num<E>::cj(s);
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_trace_shift(E *G, int64_t ldg, int n, double coef,
+                                                     int add_shift, double *out, const int *flag) {
+  __shared__ double sh[256];
+  if (flag != nullptr && flag[0] != 0) return;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += Num<E>::re(G[(int64_t)i * ldg + i]);
+  const double tr = block_sum256(v, sh);
+  const double s = coef * tr;
+  if (add_shift)
+    for (int i = threadIdx.x; i < n; i += 256) {
+      E g = G[(int64_t)i * ldg + i];
+      G[(int64_t)i * ldg + i] = g + Num<E>::real(s);
+    }
+  if (threadIdx.x == 0) {
+    out[0] = tr;
+    out[1] = add_shift ? s : 0.0;
+  }
+}
+
+// ------------------------------------------- Cholesky of a diagonal block --
+// One work-group factors the b x b (b <= 64) diagonal block of G at (p0, p0)
+// from its upper triangle (G = R^H R, right-looking), writes R and R^{-1}
+// (upper, zero below the diagonal) and reports a non-positive or non-finite
+// pivot through flag.
+template <typename E>
+__global__ __launch_bounds__(256) void k_chol_diag(const E *G, int64_t ldg, E *R, int64_t ldr,
+                                                   E *Ri, int64_t ldi, int p0, int b, int *flag,
+                                                   int pass, int inject) {
+  __shared__ E L[64][65];
+  __shared__ E X[64][65];
+  if (flag[0] != 0) return;
+  const int t = threadIdx.x;
+  if (inject) {
+    if (t == 0) { flag[0] = p0 + 1; flag[1] = pass; }
+    return;
+  }
+  for (int idx = t; idx < b * b; idx += 256) {
+    const int r = idx % b, c = idx / b;
+    L[r][c] = (r <= c) ? G[(int64_t)(p0 + c) * ldg + p0 + r] : Num<E>::zero();
+  }
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    const double d = Num<E>::re(L[j][j]);
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (t == 0) { flag[0] = p0 + j + 1; flag[1] = pass; }
+      return;
+    }
+    const double rj = sqrt(d), inv = 1.0 / rj;
+    __syncthreads();
+    for (int c = j + 1 + t; c < b; c += 256) L[j][c] = Num<E>::scale(L[j][c], inv);
+    if (t == 0) L[j][j] = Num<E>::real(rj);
+    __syncthreads();
+    for (int idx = t; idx < b * b; idx += 256) {
+      const int i = idx % b, c = idx / b;
+      if (i > j && i <= c) L[i][c] = L[i][c] - Num<E>::mul(Num<E>::cj(L[j][i]), L[j][c]);
+    }
+    __syncthreads();
+  }
+  if (t < b) {  // column t of the inverse by back substitution
+    const int c = t;
+    X[c][c] = Num<E>::real(1.0 / Num<E>::re(L[c][c]));
+    for (int i = c - 1; i >= 0; --i) {
+      E s = Num<E>::zero();
+      for (int q = i + 1; q <= c; ++q) s = s + Num<E>::mul(L[i][q], X[q][c]);
+      X[i][c] = Num<E>::scale(-s, 1.0 / Num<E>::re(L[i][i]));
+    }
+    for (int i = c + 1; i < b; ++i) X[i][c] = Num<E>::zero();
+  }
+  __syncthreads();
+  for (int idx = t; idx < b * b; idx += 256) {
+    const int r = idx % b, c = idx / b;
+    R[(int64_t)(p0 + c) * ldr + p0 + r] = (r <= c) ? L[r][c] : Num<E>::zero();
+    Ri[(int64_t)(p0 + c) * ldi + p0 + r] = X[r][c];
+  }
+}
+
+template <typename E>
+__global__ void k_fill_zero(E *A, int64_t lda, int rows, int cols) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (i < rows && j < cols) A[(int64_t)j * lda + i] = Num<E>::zero();
+}
+
+// ------------------------------------------------------------ residuals --
+template <typename E>
+__global__ __launch_bounds__(256) void k_resid(const E *HV, int64_t ldhv, const E *V, int64_t ldv,
+                                               int n, const double *theta, double *out) {
+  __shared__ double sh[256];
+  const int a = blockIdx.x;
+  const double th = theta[a];
+  const E *h = HV + (int64_t)a * ldhv;
+  const E *v = V + (int64_t)a * ldv;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const E hv = h[i], vv = v[i];
+    const double dr = Num<E>::re(hv) - th * Num<E>::re(vv);
+    const double di = Num<E>::im(hv) - th * Num<E>::im(vv);
+    s1 += dr * dr + di * di;
+    s2 += Num<E>::abs2(vv);
+  }
+  s1 = block_sum256(s1, sh);
+  s2 = block_sum256(s2, sh);
+  if (threadIdx.x == 0) out[a] = sqrt(s1) / sqrt(s2);
+}
+
+// ------------------------------------------------------- column movement --
+template <typename Ein, typename Eout>
+__global__ void k_gather(const Ein *src, int64_t lds, Eout *dst, int64_t ldd, int n,
+                         const int *perm) {
+  const int i = blockIdx.x * 256 + threadIdx.x, a = blockIdx.y;
+  if (i >= n) return;
+  const int c = perm ? perm[a] : a;
+  const Ein v = src[(int64_t)c * lds + i];
+  dst[(int64_t)a * ldd + i] = make_elem<Eout>((double)re_of(v), (double)im_of(v));
+}
+
+// -------------------------------------------------------- random blocks --
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the seed and
+// counted by (row, column); Box-Muller turns two 32-bit words into two
+// standard normal numbers.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0; c[1] = (uint32_t)p1; c[2] = n2; c[3] = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+template <typename E>
+__global__ void k_randn(E *V, int64_t ldv, int n, uint64_t seed) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (i >= n) return;
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)j, 0u, 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double u1 = ((double)c[0] + 0.5) * (1.0 / 4294967296.0);
+  const double u2 = ((double)c[1] + 0.5) * (1.0 / 4294967296.0);
+  const double rad = sqrt(-2.0 * log(u1));
+  const double z0 = rad * cos(6.283185307179586 * u2), z1 = rad * sin(6.283185307179586 * u2);
+  if (sizeof(E) == sizeof(double))
+    V[(int64_t)j * ldv + i] = make_elem<E>(z0, 0.0);
+  else
+    V[(int64_t)j * ldv + i] = make_elem<E>(z0 * 0.7071067811865476, z1 * 0.7071067811865476);
+}
+
+// ----------------------------------------------------- Lanczos helpers --
+template <typename E>
+__global__ __launch_bounds__(256) void k_dot_re(const E *v, const E *w, int n, double *out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256)
+    s += Num<E>::re(v[i]) * Num<E>::re(w[i]) + Num<E>::im(v[i]) * Num<E>::im(w[i]);
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_norm_scale(const E *w, int n, E *vout, double *beta) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += Num<E>::abs2(w[i]);
+  s = sqrt(block_sum256(s, sh));
+  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) vout[i] = Num<E>::scale(w[i], inv);
+  if (threadIdx.x == 0 && beta) *beta = s;
+}
+
+template <typename E>
+__global__ void k_sum_splits(const E *P, int nsplit, int64_t sstride, int nelem, E *out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nelem) return;
+  E s = Num<E>::zero();
+  for (int q = 0; q < nsplit; ++q) s = s + P[q * sstride + i];
+  out[i] = s;
+}
+
+// ========================================================== launchers ==
+static inline unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+#define DISPATCH_E(cplx, KERNEL, grid, block, s, ...)                                   \
+  do {                                                                                  \
+    if (cplx)                                                                           \
+      hipLaunchKernelGGL(KERNEL<double2>, grid, block, 0, s, __VA_ARGS__);              \
+    else                                                                                \
+      hipLaunchKernelGGL(KERNEL<double>, grid, block, 0, s, __VA_ARGS__);               \
+  } while (0)
+
+void reduce_hermitian(bool cplx, const void *P, int nsplit, int64_t sstride, int64_t ldp, int n,
+                      void *G, int64_t ldg, int average, hipStream_t s) {
+  if (n <= 0) return;
+  dim3 grid(blocks(n, 16), blocks(n, 16)), block(16, 16);
+  if (cplx)
+    hipLaunchKernelGGL(k_reduce_herm<double2>, grid, block, 0, s, (const double2 *)P, nsplit,
+                       sstride, ldp, n, (double2 *)G, ldg, average);
+  else
+    hipLaunchKernelGGL(k_reduce_herm<double>, grid, block, 0, s, (const double *)P, nsplit,
+                       sstride, ldp, n, (double *)G, ldg, average);
+}
+
+void trace_shift(bool cplx, void *G, int64_t ldg, int n, double coef, int add_shift,
+                 double *trace_out, const int *flag, hipStream_t s) {
+  if (cplx)
+    hipLaunchKernelGGL(k_trace_shift<double2>, dim3(1), dim3(256), 0, s, (double2 *)G, ldg, n,
+                       coef, add_shift, trace_out, flag);
+  else
+    hipLaunchKernelGGL(k_trace_shift<double>, dim3(1), dim3(256), 0, s, (double *)G, ldg, n,
+                       coef, add_shift, trace_out, flag);
+}
+
+void chol_diag(bool cplx, void *G, int64_t ldg, void *R, int64_t ldr, void *Ri, int64_t ldi,
+               int p0, int b, int *flag, int pass, int inject, hipStream_t s) {
+  if (cplx)
+    hipLaunchKernelGGL(k_chol_diag<double2>, dim3(1), dim3(256), 0, s, (const double2 *)G, ldg,
+                       (double2 *)R, ldr, (double2 *)Ri, ldi, p0, b, flag, pass, inject);
+  else
+    hipLaunchKernelGGL(k_chol_diag<double>, dim3(1), dim3(256), 0, s, (const double *)G, ldg,
+                       (double *)R, ldr, (double *)Ri, ldi, p0, b, flag, pass, inject);
+}
+
+void fill_zero(bool cplx, void *A, int64_t lda, int rows, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 grid(blocks(rows, 256), cols);
+  if (cplx)
+    hipLaunchKernelGGL(k_fill_zero<double2>, grid, dim3(256), 0, s, (double2 *)A, lda, rows, cols);
+  else
+    hipLaunchKernelGGL(k_fill_zero<double>, grid, dim3(256), 0, s, (double *)A, lda, rows, cols);
+}
+
+void residuals(bool cplx, const void *HV, int64_t ldhv, const void *V, int64_t ldv, int n,
+               int ncols, const double *theta, double *resid, hipStream_t s) {
+  if (ncols <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(k_resid<double2>, dim3(ncols), dim3(256), 0, s, (const double2 *)HV, ldhv,
+                       (const double2 *)V, ldv, n, theta, resid);
+  else
+    hipLaunchKernelGGL(k_resid<double>, dim3(ncols), dim3(256), 0, s, (const double *)HV, ldhv,
+                       (const double *)V, ldv, n, theta, resid);
+}
+
+void gather_cols(bool cplx, bool to32, const void *src, int64_t lds, void *dst, int64_t ldd,
+                 int n, int ncols, const int *perm, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  dim3 grid(blocks(n, 256), ncols);
+  if (cplx) {
+    if (to32)
+      hipLaunchKernelGGL((k_gather<double2, float2>), grid, dim3(256), 0, s, (const double2 *)src,
+                         lds, (float2 *)dst, ldd, n, perm);
+    else
+      hipLaunchKernelGGL((k_gather<double2, double2>), grid, dim3(256), 0, s,
+                         (const double2 *)src, lds, (double2 *)dst, ldd, n, perm);
+  } else {
+    if (to32)
+      hipLaunchKernelGGL((k_gather<double, float>), grid, dim3(256), 0, s, (const double *)src,
+                         lds, (float *)dst, ldd, n, perm);
+    else
+      hipLaunchKernelGGL((k_gather<double, double>), grid, dim3(256), 0, s, (const double *)src,
+                         lds, (double *)dst, ldd, n, perm);
+  }
+}
+
+void copy_cols(bool cplx, const void *src, int64_t lds, void *dst, int64_t ldd, int n, int ncols,
+               hipStream_t s) {
+  gather_cols(cplx, false, src, lds, dst, ldd, n, ncols, nullptr, s);
+}
+
+void convert_to32(bool cplx, const void *src, int64_t lds, void *dst, int64_t ldd, int rows,
+                  int cols, hipStream_t s) {
+  gather_cols(cplx, true, src, lds, dst, ldd, rows, cols, nullptr, s);
+}
+
+void randn(bool cplx, void *V, int64_t ldv, int n, int ncols, uint64_t seed, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  dim3 grid(blocks(n, 256), ncols);
+  if (cplx)
+    hipLaunchKernelGGL(k_randn<double2>, grid, dim3(256), 0, s, (double2 *)V, ldv, n, seed);
+  else
+    hipLaunchKernelGGL(k_randn<double>, grid, dim3(256), 0, s, (double *)V, ldv, n, seed);
+}
+
+void dot_re(bool cplx, const void *v, const void *w, int n, double *out, hipStream_t s) {
+  if (cplx)
+    hipLaunchKernelGGL(k_dot_re<double2>, dim3(1), dim3(256), 0, s, (const double2 *)v,
+                       (const double2 *)w, n, out);
+  else
+    hipLaunchKernelGGL(k_dot_re<double>, dim3(1), dim3(256), 0, s, (const double *)v,
+                       (const double *)w, n, out);
+}
+
+void norm_scale(bool cplx, const void *w, int n, void *vout, double *beta_out, hipStream_t s) {
+  if (cplx)
+    hipLaunchKernelGGL(k_norm_scale<double2>, dim3(1), dim3(256), 0, s, (const double2 *)w, n,
+                       (double2 *)vout, beta_out);
+  else
+    hipLaunchKernelGGL(k_norm_scale<double>, dim3(1), dim3(256), 0, s, (const double *)w, n,
+                       (double *)vout, beta_out);
+}
+
+void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int nelem, void *out,
+                hipStream_t s) {
+  if (nelem <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(k_sum_splits<double2>, dim3(blocks(nelem, 256)), dim3(256), 0, s,
+                       (const double2 *)P, nsplit, sstride, nelem, (double2 *)out);
+  else
+    hipLaunchKernelGGL(k_sum_splits<double>, dim3(blocks(nelem, 256)), dim3(256), 0, s,
+                       (const double *)P, nsplit, sstride, nelem, (double *)out);
+}
+
+// ------------------------------------------------------------- GEMM ------
+constexpr int kBK = 16;
+int gemm_bk() { return kBK; }
+
+template <typename T, bool CPLX, bool AT, int EPI, typename FT, int SHAPE>
+static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
+  constexpr int BM = SHAPE == GEMM_BIG ? 128 : 64;
+  constexpr int BN = SHAPE == GEMM_BIG ? (CPLX ? 64 : 128) : 64;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  const int nbm = (a.M + BM - 1) / BM, nbn = (a.N + BN - 1) / BN;
+  if (nbm <= 0 || nbn <= 0) return;
+  if (splits < 1) splits = 1;
+  if (a.k_per_split <= 0) a.k_per_split = ((a.K + kBK - 1) / kBK) * kBK;
+  dim3 grid((unsigned)(nbm * nbn), (unsigned)splits);
+  hipLaunchKernelGGL((gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, kBK, WM, WN, EPI, FT>), grid,
+                     dim3(256), 0, s, a);
+}
+
+void gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,
+          GemmArgs &a, int splits, hipStream_t s) {
+  if (epi_filter) {  // filter steps: A = H read K-contiguous, big tiles
+    if (prec32) {
+      if (!out64) throw InvalidArg();
+      if (cplx) gemm_launch<float, true, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
+      else gemm_launch<float, false, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
+    } else {
+      if (cplx) gemm_launch<double, true, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
+      else gemm_launch<double, false, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
+    }
+    return;
+  }
+  if (prec32) throw InvalidArg();
+#define G_CASE(C, A, S)                                                                  \
+  if (cplx == C && at == A && shape == S) {                                              \
+    gemm_launch<double, C, A, EPI_AXPBY, double, S>(a, splits, s);                       \
+    return;                                                                              \
+  }
+  G_CASE(false, false, GEMM_BIG)
+  G_CASE(false, true, GEMM_BIG)
+  G_CASE(false, false, GEMM_SMALL)
+  G_CASE(false, true, GEMM_SMALL)
+  G_CASE(true, false, GEMM_BIG)
+  G_CASE(true, true, GEMM_BIG)
+  G_CASE(true, false, GEMM_SMALL)
+  G_CASE(true, true, GEMM_SMALL)
+#undef G_CASE
+  throw InvalidArg();
+}
+
+}  // namespace chase

@@ -1,0 +1,755 @@
+// Host driver of Chebyshev filtered subspace iteration (Alg. 1 of the paper)
+// on one gfx950 GPU: workspace, the filter loop, the CholeskyQR variants of
+// Alg. 2 / Alg. 3 with a device-side failure flag, Rayleigh-Ritz, residuals,
+// locking, the degree policy and the condition-number estimate.
+#include "solver.hpp"
+
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "gemm.hpp"
+#include "kernels.hpp"
+
+namespace chase {
+
+static const double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
+
+// ------------------------------------------------------------ host logic --
+// |rho| of x for the interval [c - e, c + e] (eq:rho, convergence ratio of
+// Sec. 2.3): |t| + sqrt(t^2 - 1) outside, 1 inside.
+double rho_abs(double x, double c, double e) {
+  const double t = (x - c) / e;
+  if (std::fabs(t) <= 1.0) return 1.0;
+  return std::fabs(t) + std::sqrt(t * t - 1.0);
+}
+
+// eq:full-est with eta = 1, in log space.
+double log_cond_estimate(double theta_next, int m_next, int m_max, double lam1, double c,
+                         double e) {
+  return m_next * std::log(rho_abs(theta_next, c, e)) +
+         (double)(m_max - m_next) * std::log(rho_abs(lam1, c, e));
+}
+
+// Alg. 3 branch choice.
+chase_qr select_qr(double est, double hi, double lo) {
+  if (est > hi) return CHASE_QR_SHIFTED;
+  if (est < lo) return CHASE_QR_CHOL1;
+  return CHASE_QR_CHOL2;
+}
+
+// Per-vector degree: enough steps for the residual to fall from r to tol at
+// the rate 1/|rho(theta)| per step (Sec. 2.3), plus a margin.
+void degrees(const double *theta, const double *resid, int n, double tol, double c, double e,
+             int min_deg, int max_deg, int margin, int *out) {
+  for (int a = 0; a < n; ++a) {
+    if (resid[a] <= tol) { out[a] = min_deg; continue; }
+    const double rho = rho_abs(theta[a], c, e);
+    if (rho <= 1.0) { out[a] = max_deg; continue; }
+    const double d = std::ceil(std::log(resid[a] / tol) / std::log(rho)) + margin;
+    out[a] = (int)std::min<double>(std::max<double>(d, min_deg), max_deg);
+  }
+}
+
+// Cyclic Jacobi eigen-decomposition of a small dense symmetric matrix
+// (row-major n x n); returns ascending eigenvalues and the matching
+// eigenvectors as columns of V (row-major).
+static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w,
+                       std::vector<double> &V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double v = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        const double th = (aqq - app) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = cs * akp - sn * akq;
+          A[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = cs * apk - sn * aqk;
+          A[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    return A[(size_t)a * n + a] < A[(size_t)b * n + b];
+  });
+  w.resize(n);
+  std::vector<double> Vs((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = A[(size_t)idx[j] * n + idx[j]];
+    for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + idx[j]];
+  }
+  V.swap(Vs);
+}
+
+// Bounds from the Lanczos tridiagonal T_k: upper = largest Ritz value +
+// |beta_k|; lambda_1 estimate = smallest Ritz value; lambda_l estimate = the
+// Ritz value where the spectral-density count N |s_1j|^2 first reaches l,
+// clamped into the interval.
+void lanczos_bounds_from_tridiag(const std::vector<double> &alpha, const std::vector<double> &beta,
+                                 int64_t N, int nsearch, double bounds[3]) {
+  int k = (int)alpha.size();
+  for (int j = 0; j < k; ++j)
+    if (beta[j] == 0.0) { k = j + 1; break; }
+  std::vector<double> T((size_t)k * k, 0.0), w, V;
+  for (int j = 0; j < k; ++j) {
+    T[(size_t)j * k + j] = alpha[j];
+    if (j + 1 < k) {
+      T[(size_t)j * k + j + 1] = beta[j];
+      T[(size_t)(j + 1) * k + j] = beta[j];
+    }
+  }
+  jacobi_eig(k, T, w, V);
+  const double up = w[k - 1] + std::fabs(beta[k - 1]);
+  const double low = w[0];
+  double cum = 0.0;
+  int idx = k - 1;
+  for (int j = 0; j < k; ++j) {
+    cum += (double)N * V[j] * V[j];  // first row of the eigenvector matrix
+    if (cum >= (double)nsearch) { idx = j; break; }
+  }
+  double mid = w[idx];
+  const double span = up - low;
+  mid = std::min(std::max(mid, low + 1e-3 * span), up - 1e-3 * span);
+  bounds[0] = low;
+  bounds[1] = mid;
+  bounds[2] = up;
+}
+
+// --------------------------------------------------------------- workspace --
+static inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int gram_splits(int64_t N, int L) {
+  const int t = (L + 63) / 64;
+  const int tiles = t * (t + 1) / 2;
+  int s = (1024 + tiles - 1) / tiles;
+  const int smax = (int)std::max<int64_t>(1, N / 256);
+  s = std::min(std::min(s, smax), 32);
+  return std::max(s, 1);
+}
+static int lz_splits(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(128, N / 512)); }
+
+struct Layout {
+  size_t off[32];
+  size_t total;
+};
+
+static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
+  const size_t es = cplx ? 16 : 8;
+  const int ns = gram_splits(N, L);
+  const int lzs = lz_splits(N);
+  const int k = lz_steps > 0 ? (int)std::min<int64_t>(lz_steps, N) : 0;
+  const size_t sz[] = {
+      al(es * N * L), al(es * N * L), al(es * N * L), al(es * N * L),  // X0 B1 B2 Xq
+      al(es * (size_t)ns * L * L),                                     // P
+      al(es * L * L), al(es * L * L), al(es * L * L), al(es * L * L), al(es * L * L),  // G R Ri T A
+      al(8 * (size_t)L), al(8 * (size_t)L), al(8 * (size_t)L), al(64),  // theta resid E trace
+      al(16), al(4 * (size_t)L), al(4 * (size_t)L), al(16),              // flag deg perm rinfo
+      al(es * L),                                                         // tau
+      mixed ? al(es / 2 * (size_t)N * N) : 0,                             // H32
+      k ? al(es * (size_t)N * (k + 1)) : 0,                               // LV
+      k ? al(es * (size_t)N) : 0,                                         // LW
+      k ? al(es * (size_t)k) : 0,                                         // Lh
+      k ? al(es * (size_t)lzs * k) : 0,                                   // LhP
+      k ? al(16 * (size_t)k) : 0,                                         // lz_ab
+  };
+  Layout lo{};
+  size_t o = 0;
+  const int n = sizeof(sz) / sizeof(sz[0]);
+  for (int i = 0; i < n; ++i) {
+    lo.off[i] = o;
+    o += sz[i];
+  }
+  lo.total = o;
+  return lo;
+}
+
+size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
+  return layout(N, L, cplx, mixed, lz_steps).total;
+}
+
+void Ctx::ensure_init() {
+  if (init) return;
+  if (stream == nullptr) {
+    CHASE_HIP(hipStreamCreate(&stream));
+    own_stream = true;
+  }
+  if (rocblas_create_handle(&rb) != rocblas_status_success) {
+    set_error("rocblas_create_handle failed");
+    throw DeviceError();
+  }
+  rocblas_set_stream(rb, stream);
+  for (auto &e : ev) CHASE_HIP(hipEventCreate(&e));
+  init = true;
+}
+
+void Ctx::set_stream(hipStream_t s) {
+  ensure_init();
+  hipStream_t target = s ? s : stream;
+  rocblas_set_stream(rb, target);
+}
+
+void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
+  ensure_init();
+  if (w.base && w.N == N && w.L == L && w.cplx == cplx && w.mixed == mixed &&
+      w.lz_steps == lz_steps)
+    return;
+  Layout lo = layout(N, L, cplx, mixed, lz_steps);
+  if (w.base == nullptr || w.bytes < lo.total) {
+    if (w.base) {
+      CHASE_HIP(hipStreamSynchronize(stream));
+      CHASE_HIP(hipFree(w.base));
+      w.base = nullptr;
+      w.bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, lo.total) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc of " + std::to_string(lo.total) + " bytes of workspace failed");
+      throw OutOfMemory();
+    }
+    w.base = (char *)p;
+    w.bytes = lo.total;
+  }
+  w.N = N;
+  w.L = L;
+  w.cplx = cplx;
+  w.mixed = mixed;
+  w.lz_steps = lz_steps;
+  w.nsplit = gram_splits(N, L);
+  w.lz_split = lz_splits(N);
+  char *b = w.base;
+  int i = 0;
+  w.X0 = b + lo.off[i++]; w.B1 = b + lo.off[i++]; w.B2 = b + lo.off[i++]; w.Xq = b + lo.off[i++];
+  w.P = b + lo.off[i++];
+  w.G = b + lo.off[i++]; w.R = b + lo.off[i++]; w.Ri = b + lo.off[i++]; w.T = b + lo.off[i++];
+  w.A = b + lo.off[i++];
+  w.theta = (double *)(b + lo.off[i++]); w.resid = (double *)(b + lo.off[i++]);
+  w.E = (double *)(b + lo.off[i++]); w.trace = (double *)(b + lo.off[i++]);
+  w.flag = (int *)(b + lo.off[i++]); w.deg = (int *)(b + lo.off[i++]);
+  w.perm = (int *)(b + lo.off[i++]); w.rinfo = (int *)(b + lo.off[i++]);
+  w.tau = b + lo.off[i++];
+  w.H32 = mixed ? (void *)(b + lo.off[i]) : nullptr; i++;
+  w.LV = b + lo.off[i++]; w.LW = b + lo.off[i++]; w.Lh = b + lo.off[i++]; w.LhP = b + lo.off[i++];
+  w.lz_ab = (double *)(b + lo.off[i++]);
+  // pinned host mirrors, grown on demand
+  if (L > h_cap_L || std::max(lz_steps, 1) > h_cap_lz) {
+    CHASE_HIP(hipStreamSynchronize(stream));
+    free_pinned();
+    h_cap_L = std::max(L, h_cap_L);
+    h_cap_lz = std::max(std::max(lz_steps, 1), h_cap_lz);
+    CHASE_HIP(hipHostMalloc((void **)&w.h_theta, 8 * (size_t)h_cap_L));
+    CHASE_HIP(hipHostMalloc((void **)&w.h_resid, 8 * (size_t)h_cap_L));
+    CHASE_HIP(hipHostMalloc((void **)&w.h_ab, 16 * (size_t)h_cap_lz));
+    CHASE_HIP(hipHostMalloc((void **)&w.h_flag, 16));
+    CHASE_HIP(hipHostMalloc((void **)&w.h_ints, 8 * (size_t)h_cap_L));
+  }
+}
+
+void Ctx::free_pinned() {
+  if (w.h_theta) (void)hipHostFree(w.h_theta);
+  if (w.h_resid) (void)hipHostFree(w.h_resid);
+  if (w.h_ab) (void)hipHostFree(w.h_ab);
+  if (w.h_flag) (void)hipHostFree(w.h_flag);
+  if (w.h_ints) (void)hipHostFree(w.h_ints);
+  w.h_theta = w.h_resid = w.h_ab = nullptr;
+  w.h_flag = w.h_ints = nullptr;
+  h_cap_L = h_cap_lz = 0;
+}
+
+void Ctx::release() {
+  if (w.base) (void)hipFree(w.base);
+  free_pinned();
+  w = Work();
+  if (init) {
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    rocblas_destroy_handle(rb);
+    if (own_stream) (void)hipStreamDestroy(stream);
+  }
+  init = false;
+  stream = nullptr;
+  own_stream = false;
+}
+
+Ctx &thread_ctx() {
+  static thread_local Ctx *c = new Ctx();  // lives until the process ends
+  return *c;
+}
+
+// ------------------------------------------------------------------ steps --
+static GemmArgs gargs() {
+  GemmArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.alpha = 1.0;
+  return a;
+}
+
+// Alg. 4 with per-vector degrees: one filter-GEMM launch per degree step,
+// each on the active suffix of the degree-sorted block.
+int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, void *bufs[3],
+           int64_t ldb, int ncols, const int *deg_dev, const std::vector<int> &deg_sorted,
+           double cc, double e, double gamma, void *out, int64_t ldo) {
+  if (ncols <= 0) return 0;
+  const double sigma1 = e / (gamma - cc);
+  double s = sigma1, sprev = 0.0;
+  const int mmax = deg_sorted.back();
+  int launches = 0;
+  for (int step = 1; step <= mmax; ++step) {
+    const int start =
+        (int)(std::lower_bound(deg_sorted.begin(), deg_sorted.end(), step) - deg_sorted.begin());
+    GemmArgs a = gargs();
+    a.A = H; a.lda = ldh;
+    a.B = bufs[(step - 1) % 3]; a.ldb = ldb;
+    a.M = (int)N; a.N = ncols - start; a.K = (int)N;
+    a.col0 = start;
+    a.alpha = (step == 1 ? 1.0 : 2.0) * s / e;
+    a.beta = step == 1 ? 0.0 : -sprev * s;
+    a.shift = cc;
+    a.Xprev = bufs[(step + 1) % 3]; a.ldp = ldb;
+    a.Onext = bufs[step % 3]; a.ldn = ldb;
+    a.Ofinal = out; a.ldf = ldo;
+    a.deg = deg_dev; a.step = step;
+    gemm(cplx, f32, true, true, true, GEMM_BIG, a, 1, c.stream);
+    ++launches;
+    sprev = s;
+    s = 1.0 / (2.0 / sigma1 - s);
+  }
+  CHASE_HIP(hipGetLastError());
+  return launches;
+}
+
+// G = X^H X (upper triangle by tiles, deterministic split-K) -> Hermitian G.
+static void gram(Ctx &c, bool cplx, const void *X, int64_t ldx, int64_t N, int L, void *G,
+                 int average_with_B, const void *B = nullptr, int64_t ldB = 0) {
+  Work &w = c.w;
+  // partials buffer holds w.nsplit * w.L^2 elements: never use more splits
+  const int64_t cap = (int64_t)w.nsplit * w.L * w.L / ((int64_t)L * L);
+  const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(gram_splits(N, L), cap));
+  const int bk = gemm_bk();
+  GemmArgs a = gargs();
+  a.A = X; a.lda = ldx;
+  a.B = B ? B : X; a.ldb = B ? ldB : ldx;
+  a.M = L; a.N = L; a.K = (int)N;
+  a.tri = average_with_B ? 0 : 1;
+  a.k_per_split = (int)(((N + ns - 1) / ns + bk - 1) / bk * bk);
+  a.C = w.P; a.ldc = L; a.split_stride = (int64_t)L * L;
+  a.flag = average_with_B ? nullptr : w.flag;
+  gemm(cplx, false, true, false, false, GEMM_SMALL, a, ns, c.stream);
+  reduce_hermitian(cplx, w.P, ns, (int64_t)L * L, L, L, G, L, average_with_B, c.stream);
+}
+
+// Blocked right-looking Cholesky G = R^H R (upper), R^{-1} alongside.
+static void potrf(Ctx &c, bool cplx, int L, int pass, int inject) {
+  Work &w = c.w;
+  const int nb = 64;
+  const int nbk = (L + nb - 1) / nb;
+  fill_zero(cplx, w.Ri, L, L, L, c.stream);
+  for (int p = 0; p < nbk; ++p) {
+    const int p0 = p * nb, b = std::min(nb, L - p0);
+    chol_diag(cplx, w.G, L, w.R, L, w.Ri, L, p0, b, w.flag, pass, inject && p == 0, c.stream);
+    const int rest = L - p0 - b;
+    if (rest <= 0) continue;
+    const size_t es = cplx ? 16 : 8;
+    {  // R[p-block, right] = Ri_pp^H G[p-block, right]
+      GemmArgs a = gargs();
+      a.A = (char *)w.Ri + es * ((size_t)p0 + (size_t)p0 * L); a.lda = L;
+      a.B = (char *)w.G + es * p0; a.ldb = L; a.col0 = p0 + b;
+      a.M = b; a.N = rest; a.K = b;
+      a.C = (char *)w.R + es * p0; a.ldc = L; a.ccol0 = p0 + b;
+      a.flag = w.flag;
+      gemm(cplx, false, true, false, false, GEMM_SMALL, a, 1, c.stream);
+    }
+    {  // G[right, right] -= R[p-block, right]^H R[p-block, right]
+      GemmArgs a = gargs();
+      a.A = (char *)w.R + es * ((size_t)p0 + (size_t)(p0 + b) * L); a.lda = L;
+      a.B = (char *)w.R + es * p0; a.ldb = L; a.col0 = p0 + b;
+      a.M = rest; a.N = rest; a.K = b;
+      a.C = (char *)w.G + es * (p0 + b); a.ldc = L; a.ccol0 = p0 + b;
+      a.alpha = -1.0; a.beta = 1.0; a.tri = 1;
+      a.flag = w.flag;
+      gemm(cplx, false, true, false, false, GEMM_SMALL, a, 1, c.stream);
+    }
+  }
+  // off-diagonal blocks of R^{-1}, left to right:
+  // Ri[0:J, J-block] = -(Ri[0:J, 0:J] R[0:J, J-block]) Ri_JJ
+  const size_t es = cplx ? 16 : 8;
+  for (int jb = 1; jb < nbk; ++jb) {
+    const int J = jb * nb, b = std::min(nb, L - J);
+    {
+      GemmArgs a = gargs();
+      a.A = w.Ri; a.lda = L;
+      a.B = w.R; a.ldb = L; a.col0 = J;
+      a.M = J; a.N = b; a.K = J;
+      a.C = w.T; a.ldc = J; a.ccol0 = 0;
+      a.flag = w.flag;
+      gemm(cplx, false, false, false, false, GEMM_SMALL, a, 1, c.stream);
+    }
+    {
+      GemmArgs a = gargs();
+      a.A = w.T; a.lda = J;
+      a.B = (char *)w.Ri + es * J; a.ldb = L; a.col0 = J;
+      a.M = J; a.N = b; a.K = b;
+      a.C = w.Ri; a.ldc = L; a.ccol0 = J;
+      a.alpha = -1.0;
+      a.flag = w.flag;
+      gemm(cplx, false, false, false, false, GEMM_SMALL, a, 1, c.stream);
+    }
+  }
+}
+
+// Xout = Xin R^{-1} (R^{-1} upper triangular: K range capped per column block).
+static void trsm(Ctx &c, bool cplx, const void *Xin, void *Xout, int64_t ld, int64_t N, int L) {
+  GemmArgs a = gargs();
+  a.A = Xin; a.lda = ld;
+  a.B = c.w.Ri; a.ldb = L;
+  a.M = (int)N; a.N = L; a.K = L;
+  a.kcap = 1;
+  a.C = Xout; a.ldc = ld;
+  a.flag = c.w.flag;
+  gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);
+}
+
+static void rocsolver_check(rocblas_status st, const char *what) {
+  if (st != rocblas_status_success) {
+    set_error(std::string(what) + " failed with rocblas status " + std::to_string((int)st));
+    throw DeviceError();
+  }
+}
+
+static void householder(Ctx &c, bool cplx, void *X, int64_t ld, int64_t N, int L) {
+  if (cplx) {
+    rocsolver_check(rocsolver_zgeqrf(c.rb, (rocblas_int)N, L, (rocblas_double_complex *)X,
+                                     (rocblas_int)ld, (rocblas_double_complex *)c.w.tau),
+                    "rocsolver_zgeqrf");
+    rocsolver_check(rocsolver_zungqr(c.rb, (rocblas_int)N, L, L, (rocblas_double_complex *)X,
+                                     (rocblas_int)ld, (rocblas_double_complex *)c.w.tau),
+                    "rocsolver_zungqr");
+  } else {
+    rocsolver_check(rocsolver_dgeqrf(c.rb, (rocblas_int)N, L, (double *)X, (rocblas_int)ld,
+                                     (double *)c.w.tau),
+                    "rocsolver_dgeqrf");
+    rocsolver_check(rocsolver_dorgqr(c.rb, (rocblas_int)N, L, L, (double *)X, (rocblas_int)ld,
+                                     (double *)c.w.tau),
+                    "rocsolver_dorgqr");
+  }
+}
+
+// Alg. 3 for one variant.  The passes of CholeskyQR (Alg. 2) alternate
+// between X and Xalt; after a failed Cholesky every later kernel of the QR
+// sees the flag and does nothing, so the input of the failing pass is intact
+// and the Householder QR is applied to it.
+QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, chase_qr variant,
+         int inject) {
+  Work &w = c.w;
+  if (variant == CHASE_QR_HOUSEHOLDER) {
+    householder(c, cplx, X, ld, N, L);
+    return {X, false, CHASE_QR_HOUSEHOLDER};
+  }
+  int npass = variant == CHASE_QR_CHOL1 ? 1 : variant == CHASE_QR_CHOL2 ? 2 : 3;
+  const bool shifted = variant == CHASE_QR_SHIFTED;
+  fill_zero(false, w.flag, 1, 1, 1, c.stream);  // two ints
+  void *in = X;
+  void *inputs[3];
+  const double coef = 11.0 * ((double)N * L + (double)L * (L + 1)) * kUnitRoundoff;
+  for (int q = 0; q < npass; ++q) {
+    void *out = (in == X) ? Xalt : X;
+    inputs[q] = in;
+    gram(c, cplx, in, ld, N, L, w.G, 0);
+    if (shifted && q == 0) trace_shift(cplx, w.G, L, L, coef, 1, w.trace, w.flag, c.stream);
+    potrf(c, cplx, L, q, inject && q == 0);
+    trsm(c, cplx, in, out, ld, N, L);
+    in = out;
+  }
+  CHASE_HIP(hipGetLastError());
+  CHASE_HIP(hipMemcpyAsync(w.h_flag, w.flag, 8, hipMemcpyDeviceToHost, c.stream));
+  CHASE_HIP(hipStreamSynchronize(c.stream));
+  if (w.h_flag[0] != 0) {
+    const int fp = std::min(std::max(w.h_flag[1], 0), npass - 1);
+    householder(c, cplx, inputs[fp], ld, N, L);
+    return {inputs[fp], true, CHASE_QR_HOUSEHOLDER};
+  }
+  return {in, false, variant};
+}
+
+// Rayleigh-Ritz on the orthonormal Q (N x Lp): W = H Q, A~ = Q^H W
+// symmetrised, (theta, Z) = eigh(A~), V = Q Z, HV = W Z.
+void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *Q,
+                   int64_t ldq, int Lp, void *W, void *Vout, int64_t ldv, void *HV, int64_t ldhv) {
+  Work &w = c.w;
+  {
+    GemmArgs a = gargs();
+    a.A = H; a.lda = ldh;
+    a.B = Q; a.ldb = ldq;
+    a.M = (int)N; a.N = Lp; a.K = (int)N;
+    a.C = W; a.ldc = N;
+    gemm(cplx, false, true, false, false, GEMM_BIG, a, 1, c.stream);
+  }
+  gram(c, cplx, Q, ldq, N, Lp, w.A, 1, W, N);
+  rocblas_status st;
+  if (cplx)
+    st = rocsolver_zheevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp,
+                          (rocblas_double_complex *)w.A, Lp, w.theta, w.E, w.rinfo);
+  else
+    st = rocsolver_dsyevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp, (double *)w.A, Lp,
+                          w.theta, w.E, w.rinfo);
+  rocsolver_check(st, cplx ? "rocsolver_zheevd" : "rocsolver_dsyevd");
+  {
+    GemmArgs a = gargs();
+    a.A = Q; a.lda = ldq;
+    a.B = w.A; a.ldb = Lp;
+    a.M = (int)N; a.N = Lp; a.K = Lp;
+    a.C = Vout; a.ldc = ldv;
+    gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);
+  }
+  {
+    GemmArgs a = gargs();
+    a.A = W; a.lda = N;
+    a.B = w.A; a.ldb = Lp;
+    a.M = (int)N; a.N = Lp; a.K = Lp;
+    a.C = HV; a.ldc = ldhv;
+    gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);
+  }
+  CHASE_HIP(hipGetLastError());
+}
+
+// k Lanczos steps with full reorthogonalisation (classical Gram-Schmidt,
+// twice); alpha/beta returned on the host.
+void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *v0, int steps,
+             uint64_t seed, std::vector<double> &alpha, std::vector<double> &beta) {
+  Work &w = c.w;
+  const int k = (int)std::min<int64_t>(steps, N);
+  const size_t es = cplx ? 16 : 8;
+  const int nsl = lz_splits(N);
+  const int bk = gemm_bk();
+  if (v0)
+    CHASE_HIP(hipMemcpyAsync(w.LW, v0, es * N, hipMemcpyDeviceToDevice, c.stream));
+  else
+    randn(cplx, w.LW, N, (int)N, 1, seed, c.stream);
+  norm_scale(cplx, w.LW, (int)N, w.LV, nullptr, c.stream);
+  for (int j = 0; j < k; ++j) {
+    void *vj = (char *)w.LV + es * (size_t)N * j;
+    {
+      GemmArgs a = gargs();
+      a.A = H; a.lda = ldh;
+      a.B = vj; a.ldb = N;
+      a.M = (int)N; a.N = 1; a.K = (int)N;
+      a.C = w.LW; a.ldc = N;
+      gemm(cplx, false, true, false, false, GEMM_BIG, a, 1, c.stream);
+    }
+    dot_re(cplx, vj, w.LW, (int)N, w.lz_ab + j, c.stream);
+    for (int rep = 0; rep < 2; ++rep) {
+      GemmArgs a = gargs();
+      a.A = w.LV; a.lda = N;
+      a.B = w.LW; a.ldb = N;
+      a.M = j + 1; a.N = 1; a.K = (int)N;
+      a.k_per_split = (int)(((N + nsl - 1) / nsl + bk - 1) / bk * bk);
+      a.C = w.LhP; a.ldc = k; a.split_stride = k;
+      gemm(cplx, false, true, false, false, GEMM_SMALL, a, nsl, c.stream);
+      sum_splits(cplx, w.LhP, nsl, k, j + 1, w.Lh, c.stream);
+      GemmArgs b = gargs();
+      b.A = w.LV; b.lda = N;
+      b.B = w.Lh; b.ldb = k;
+      b.M = (int)N; b.N = 1; b.K = j + 1;
+      b.C = w.LW; b.ldc = N;
+      b.alpha = -1.0; b.beta = 1.0;
+      gemm(cplx, false, false, false, false, GEMM_BIG, b, 1, c.stream);
+    }
+    norm_scale(cplx, w.LW, (int)N, (char *)w.LV + es * (size_t)N * (j + 1), w.lz_ab + k + j,
+               c.stream);
+  }
+  CHASE_HIP(hipGetLastError());
+  CHASE_HIP(hipMemcpyAsync(w.h_ab, w.lz_ab, 16 * (size_t)k, hipMemcpyDeviceToHost, c.stream));
+  CHASE_HIP(hipStreamSynchronize(c.stream));
+  alpha.assign(w.h_ab, w.h_ab + k);
+  beta.assign(w.h_ab + k, w.h_ab + 2 * k);
+}
+
+// -------------------------------------------------------------- the solve --
+static double elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.0;
+  }
+  return ms * 1e-3;
+}
+
+chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_t ldh, int nev,
+                   int nex, int degree, double tol, double *evals, void *evecs, int64_t ldv,
+                   double *resid, chase_info *info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const bool cplx = o.dtype == CHASE_COMPLEX128;
+  const bool mixed = o.precision == CHASE_PREC_MIXED;
+  const int L = nev + nex;
+  const size_t es = cplx ? 16 : 8;
+  const int lz = o.have_bounds ? 0 : std::max(1, o.lanczos_steps);
+  c.ensure_work(N, L, cplx, mixed, lz);
+  Work &w = c.w;
+  hipStream_t s = c.stream;
+  chase_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+
+  // spectral bounds (Alg. 1: lambda_1, lambda_l, upper bound of lambda_n)
+  double gamma, alpha, beta;
+  if (o.have_bounds) {
+    gamma = o.lambda_1; alpha = o.lambda_l; beta = o.lambda_max;
+  } else {
+    CHASE_HIP(hipEventRecord(c.ev[6], s));
+    std::vector<double> la, lb;
+    lanczos(c, cplx, H, ldh, N, o.lanczos_v0, lz, o.seed + 0x9E3779B97F4A7C15ull, la, lb);
+    CHASE_HIP(hipEventRecord(c.ev[7], s));
+    double bd[3];
+    lanczos_bounds_from_tridiag(la, lb, N, L, bd);
+    gamma = bd[0]; alpha = bd[1]; beta = bd[2];
+    CHASE_HIP(hipEventSynchronize(c.ev[7]));
+    inf.t_lanczos = elapsed(c.ev[6], c.ev[7]);
+  }
+  inf.lambda_1 = gamma; inf.lambda_l = alpha; inf.lambda_max = beta;
+
+  // start block and step 0 (CholeskyQR2 of the start block)
+  if (!o.warm_start) randn(cplx, evecs, ldv, (int)N, L, o.seed, s);
+  copy_cols(cplx, evecs, ldv, w.Xq, N, (int)N, L, s);
+  {
+    QrOut q0 = qr(c, cplx, w.Xq, w.B1, N, N, L, CHASE_QR_CHOL2, 0);
+    copy_cols(cplx, q0.Q, N, evecs, ldv, (int)N, L, s);
+  }
+  if (mixed) convert_to32(cplx, H, ldh, w.H32, N, (int)N, (int)N, s);
+
+  int k = 0;
+  std::vector<int> m(L, degree);
+  std::vector<double> theta_act, r_act, lam, res_locked;
+  double lam1 = gamma;
+  int it = 0;
+  const double sw = o.mixed_switch * std::max(std::fabs(gamma), std::fabs(beta));
+  bool filter32 = mixed;
+  for (it = 1; it <= o.max_iter; ++it) {
+    const double cc = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+    const int Lp = L - k;
+    // degree-sorted order of the active columns (stable)
+    std::vector<int> order(Lp);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m[a] < m[b]; });
+    std::vector<int> msorted(Lp);
+    for (int a = 0; a < Lp; ++a) {
+      msorted[a] = m[order[a]];
+      w.h_ints[a] = order[a] + k;
+    }
+    CHASE_HIP(hipMemcpyAsync(w.perm, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
+    CHASE_HIP(hipStreamSynchronize(s));  // h_ints is reused below
+    for (int a = 0; a < Lp; ++a) w.h_ints[a] = msorted[a];
+    CHASE_HIP(hipMemcpyAsync(w.deg, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
+    if (mixed && !theta_act.empty()) {
+      double rmin = *std::min_element(r_act.begin(), r_act.end());
+      filter32 = filter32 && rmin > sw;
+    }
+    const bool f32 = mixed && filter32;
+    gather_cols(cplx, f32, evecs, ldv, w.X0, N, (int)N, Lp, w.perm, s);
+    void *bufs[3] = {w.X0, w.B1, w.B2};
+    CHASE_HIP(hipEventRecord(c.ev[0], s));
+    const int nl = filter(c, cplx, f32, f32 ? w.H32 : H, f32 ? N : ldh, N, bufs, N, Lp, w.deg,
+                          msorted, cc, e, gamma, (char *)w.Xq + es * (size_t)k * N, N);
+    CHASE_HIP(hipEventRecord(c.ev[1], s));
+    inf.filter_launches += nl;
+    if (f32) inf.filter_fp32_iters++;
+    int64_t mv = 0;
+    int mmax = 0, mmin = 1 << 30;
+    for (int a = 0; a < Lp; ++a) { mv += m[a]; mmax = std::max(mmax, m[a]); mmin = std::min(mmin, m[a]); }
+    inf.matvecs += mv;
+    // eq:full-est: theta_{k+1} = lowest unconverged Ritz value, m[0] its degree
+    const double th_next = theta_act.empty() ? gamma : theta_act[0];
+    const double lest = log_cond_estimate(th_next, m[0], mmax, lam1, cc, e);
+    const double est = lest < 709.0 ? std::exp(lest) : INFINITY;
+    chase_qr variant = o.qr_policy == CHASE_QR_AUTO ? select_qr(est, o.est_hi, o.est_lo)
+                                                     : o.qr_policy;
+    // [Y | filtered]
+    if (k > 0) copy_cols(cplx, evecs, ldv, w.Xq, N, (int)N, k, s);
+    QrOut q = qr(c, cplx, w.Xq, w.B1, N, N, L, variant, o.inject_chol_fail_iter == it);
+    CHASE_HIP(hipEventRecord(c.ev[2], s));
+    void *Q2 = (char *)q.Q + es * (size_t)k * N;
+    void *Vout = (char *)evecs + es * (size_t)k * ldv;
+    rayleigh_ritz(c, cplx, H, ldh, N, Q2, N, Lp, w.B2, Vout, ldv, w.X0, N);
+    CHASE_HIP(hipEventRecord(c.ev[3], s));
+    residuals(cplx, w.X0, N, Vout, ldv, (int)N, Lp, w.theta, w.resid, s);
+    CHASE_HIP(hipEventRecord(c.ev[4], s));
+    CHASE_HIP(hipMemcpyAsync(w.h_theta, w.theta, 8 * (size_t)Lp, hipMemcpyDeviceToHost, s));
+    CHASE_HIP(hipMemcpyAsync(w.h_resid, w.resid, 8 * (size_t)Lp, hipMemcpyDeviceToHost, s));
+    CHASE_HIP(hipStreamSynchronize(s));
+    chase_iter_log rec;
+    std::memset(&rec, 0, sizeof(rec));
+    rec.t_filter = elapsed(c.ev[0], c.ev[1]);
+    rec.t_qr = elapsed(c.ev[1], c.ev[2]);
+    rec.t_rr = elapsed(c.ev[2], c.ev[3]);
+    rec.t_resid = elapsed(c.ev[3], c.ev[4]);
+    inf.t_filter += rec.t_filter; inf.t_qr += rec.t_qr; inf.t_rr += rec.t_rr;
+    inf.t_resid += rec.t_resid;
+    std::vector<double> th(w.h_theta, w.h_theta + Lp), rr(w.h_resid, w.h_resid + Lp);
+    int j = k;
+    while (j < nev && rr[j - k] < tol) ++j;
+    const int newly = j - k;
+    for (int a = 0; a < newly; ++a) { lam.push_back(th[a]); res_locked.push_back(rr[a]); }
+    rec.iter = it; rec.locked = k; rec.newly_locked = newly; rec.qr_variant = q.ran;
+    rec.chol_failed = q.failed; rec.filter_prec = f32 ? CHASE_PREC_MIXED : CHASE_PREC_FP64;
+    rec.deg_min = mmin; rec.deg_max = mmax; rec.matvecs = mv; rec.cond_est = est;
+    rec.c = cc; rec.e = e; rec.gamma = gamma; rec.lam1 = lam1;
+    if (o.log_cb) o.log_cb(&rec, o.log_user);
+    k = j;
+    theta_act.assign(th.begin() + newly, th.end());
+    r_act.assign(rr.begin() + newly, rr.end());
+    if (k >= nev) break;
+    lam1 = k > 0 ? lam[0] : th[0];
+    gamma = theta_act[0];
+    alpha = th.back();
+    const double c2 = 0.5 * (alpha + beta), e2 = 0.5 * (beta - alpha);
+    m.assign(L - k, degree);
+    if (o.deg_opt)
+      degrees(theta_act.data(), r_act.data(), L - k, tol, c2, e2, o.min_deg, o.max_deg,
+              o.deg_margin, m.data());
+  }
+  if (it > o.max_iter) it = o.max_iter;
+  // outputs
+  for (int a = 0; a < nev; ++a) {
+    if (a < k) {
+      evals[a] = lam[a];
+      if (resid) resid[a] = res_locked[a];
+    } else {
+      evals[a] = theta_act[a - k];
+      if (resid) resid[a] = r_act[a - k];
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  inf.iters = it;
+  inf.converged = k;
+  inf.t_total = std::chrono::duration<double>(t1 - t0).count();
+  if (info) *info = inf;
+  return k >= nev ? CHASE_OK : CHASE_NOT_CONVERGED;
+}
+
+}  // namespace chase

@@ -1,0 +1,84 @@
+// Internal interface of the host driver (not part of the C ABI).
+#pragma once
+#include <rocblas/rocblas.h>
+
+#include <vector>
+
+#include "../../include/chase.h"
+#include "common.hpp"
+
+namespace chase {
+
+// Device workspace of one solve shape, carved out of a single allocation.
+struct Work {
+  int64_t N = 0;
+  int L = 0;
+  bool cplx = false, mixed = false;
+  int nsplit = 1, lz_steps = 0, lz_split = 1;
+  char *base = nullptr;
+  size_t bytes = 0;
+  void *X0 = nullptr, *B1 = nullptr, *B2 = nullptr, *Xq = nullptr;  // N x L
+  void *P = nullptr;                                                  // nsplit x L x L
+  void *G = nullptr, *R = nullptr, *Ri = nullptr, *T = nullptr, *A = nullptr;  // L x L
+  double *theta = nullptr, *resid = nullptr, *E = nullptr, *trace = nullptr;
+  int *flag = nullptr, *deg = nullptr, *perm = nullptr, *rinfo = nullptr;
+  void *tau = nullptr;
+  void *H32 = nullptr;                                  // N x N in FP32 (mixed)
+  void *LV = nullptr, *LW = nullptr, *Lh = nullptr, *LhP = nullptr;  // Lanczos
+  double *lz_ab = nullptr;
+  // pinned host mirrors
+  double *h_theta = nullptr, *h_resid = nullptr, *h_ab = nullptr;
+  int *h_flag = nullptr, *h_ints = nullptr;
+};
+
+size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps);
+
+// Per-thread (or per-handle) execution context.
+struct Ctx {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rocblas_handle rb = nullptr;
+  Work w;
+  hipEvent_t ev[8] = {};
+  bool init = false;
+  int h_cap_L = 0, h_cap_lz = 0;
+  void ensure_init();
+  void free_pinned();
+  void ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps);
+  void set_stream(hipStream_t s);
+  void release();
+};
+
+Ctx &thread_ctx();
+
+// Host logic shared with the C ABI (pure functions).
+double rho_abs(double x, double c, double e);
+double log_cond_estimate(double theta_next, int m_next, int m_max, double lam1, double c,
+                         double e);
+chase_qr select_qr(double est, double hi, double lo);
+void degrees(const double *theta, const double *resid, int n, double tol, double c, double e,
+             int min_deg, int max_deg, int margin, int *out);
+void lanczos_bounds_from_tridiag(const std::vector<double> &alpha, const std::vector<double> &beta,
+                                 int64_t N, int nsearch, double bounds[3]);
+
+// Steps (device buffers; enqueue on ctx.stream).
+int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, void *bufs[3],
+           int64_t ldb, int ncols, const int *deg_dev, const std::vector<int> &deg_sorted,
+           double cc, double e, double gamma, void *out, int64_t ldo);
+struct QrOut {
+  void *Q;
+  bool failed;
+  chase_qr ran;
+};
+QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, chase_qr variant,
+         int inject);
+void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *Q,
+                   int64_t ldq, int Lp, void *W, void *Vout, int64_t ldv, void *HV, int64_t ldhv);
+void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *v0, int steps,
+             uint64_t seed, std::vector<double> &alpha, std::vector<double> &beta);
+
+chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_t ldh, int nev,
+                   int nex, int degree, double tol, double *evals, void *evecs, int64_t ldv,
+                   double *resid, chase_info *info);
+
+}  // namespace chase

@@ -1,0 +1,135 @@
+"""End-to-end parity of chase_solve (Alg. 1 on the GPU) with the oracle, on
+the same start block and bounds: eigenvalues, residuals, the per-iteration
+QR choice and the convergence history."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import solver as osolver
+
+from gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P(gpu):
+    import paper_2603_10514_amd as P
+    return P
+
+
+def _run(P, gpu, H, lam, nev, nex, cplx, seed, **kw):
+    N = H.shape[0]
+    L = nev + nex
+    V0 = synth.start_block(N, L, seed, cplx)
+    bounds = (lam[0], lam[L - 1], lam[-1])
+    ref = osolver.chase_solve(H, nev, nex, 20, 1e-10, V0=V0, bounds=bounds,
+                              **{k: v for k, v in kw.items() if k in ("qr_policy", "deg_opt", "max_iter")})
+    ev = to_dev(V0, gpu)
+    pk = dict(warm_start=1, have_bounds=1, lambda_1=bounds[0], lambda_l=bounds[1],
+              lambda_max=bounds[2])
+    pk.update(kw)
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=ev, **pk)
+    return ref, out
+
+
+def test_config_small_real_matches_oracle(P, gpu):
+    """Real symmetric N = 1000, lambda ~ U[-1, 1], nev 40, nex 20, degree 20,
+    tol 1e-10 (the small configuration the oracle finishes in seconds)."""
+    N, nev, nex = 1000, 40, 20
+    H, lam = synth.planted_numpy(N, "uniform", 1)
+    ref, out = _run(P, gpu, H, lam, nev, nex, False, 11)
+    assert out["status"] == P.CHASE_OK and ref.converged == nev
+    scale = np.max(np.abs(lam))
+    assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10 * scale
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10 * scale
+    assert np.all(out["resid"] < 1e-10)
+    # same history: iterations, QR choice per iteration, locking
+    assert out["info"]["iters"] == ref.iters
+    assert [r["variant"] for r in out["log"]] == [r["variant"] for r in ref.log]
+    assert [r["locked"] for r in out["log"]] == [r["locked"] for r in ref.log]
+    assert abs(out["info"]["matvecs"] - ref.matvecs) <= 0.02 * ref.matvecs
+    for g, o in zip(out["log"], ref.log):
+        assert g["cond_est"] == pytest.approx(o["cond_est"], rel=1e-6)
+    Y = to_host(out["evecs"])[:, :nev]
+    assert np.linalg.norm(Y.T @ Y - np.eye(nev)) < 1e-12
+    R = H @ Y - Y * out["evals"][None, :]
+    assert np.max(np.linalg.norm(R, axis=0)) < 1e-10
+
+
+def test_complex_dft_family_matches_oracle(P, gpu):
+    N, nev, nex = 800, 40, 16
+    H, lam = synth.planted_numpy(N, "dft", 2, True)
+    ref, out = _run(P, gpu, H, lam, nev, nex, True, 12, max_deg=36)
+    assert out["status"] == P.CHASE_OK
+    scale = np.max(np.abs(lam))
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10 * scale
+    assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10 * scale
+    assert np.all(out["resid"] < 1e-10)
+    assert out["info"]["iters"] == ref.iters
+
+
+@pytest.mark.parametrize("policy", ["householder", "chol2", "shifted"])
+def test_forced_variants_converge_identically(P, gpu, policy):
+    N, nev, nex = 500, 20, 10
+    H, lam = synth.planted_numpy(N, "uniform", 7)
+    ref, out = _run(P, gpu, H, lam, nev, nex, False, 8, qr_policy=policy)
+    assert out["status"] == P.CHASE_OK
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10
+    assert all(r["variant"] == policy for r in out["log"])
+    assert out["info"]["iters"] == ref.iters
+
+
+def test_injected_cholesky_failure_falls_back(P, gpu):
+    N, nev, nex = 500, 20, 10
+    H, lam = synth.planted_numpy(N, "uniform", 9)
+    ref, out = _run(P, gpu, H, lam, nev, nex, False, 10, inject_chol_fail_iter=2)
+    assert out["status"] == P.CHASE_OK
+    rec = out["log"][1]
+    assert rec["chol_failed"] == 1 and rec["variant"] == "householder"
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10
+
+
+def test_not_converged_status(P, gpu):
+    N, nev, nex = 300, 12, 6
+    H, lam = synth.planted_numpy(N, "uniform", 5)
+    ref, out = _run(P, gpu, H, lam, nev, nex, False, 6, max_iter=1, deg_opt=0)
+    assert out["status"] == P.CHASE_NOT_CONVERGED
+    assert out["info"]["converged"] == ref.converged < nev
+
+
+def test_lanczos_bounds_path(P, gpu):
+    """No bounds given: both sides estimate them by Lanczos from the same
+    start vector."""
+    N, nev, nex = 1000, 40, 20
+    H, lam = synth.planted_numpy(N, "uniform", 1)
+    V0 = synth.start_block(N, nev + nex, 11)
+    v0 = synth.lanczos_start(N, 12)
+    ref = osolver.chase_solve(H, nev, nex, 20, 1e-10, V0=V0, lanczos_v0=v0)
+    v0d = to_dev(v0, gpu)
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=to_dev(V0, gpu), warm_start=1,
+                        lanczos_v0=v0d.data_ptr())
+    assert out["status"] == P.CHASE_OK
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10
+    assert out["info"]["lambda_max"] == pytest.approx(ref.bounds[2], rel=1e-9)
+    assert out["info"]["iters"] == ref.iters
+
+
+def test_tiny_and_full_search_space(P, gpu):
+    # nev + nex == N: the search space is the whole space
+    N, nev, nex = 64, 8, 56
+    H, lam = synth.planted_numpy(N, "uniform", 3)
+    V0 = synth.start_block(N, N, 4)
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=to_dev(V0, gpu), warm_start=1,
+                        have_bounds=1, lambda_1=lam[0], lambda_l=lam[-2], lambda_max=lam[-1] + 1e-3)
+    assert out["status"] == P.CHASE_OK
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10
+
+
+def test_random_start_block_default_path(P, gpu):
+    """No warm start and no bounds: the library draws its own start block."""
+    N, nev, nex = 700, 30, 15
+    H, lam = synth.planted_numpy(N, "uniform", 17)
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, seed=5)
+    assert out["status"] == P.CHASE_OK
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10

@@ -1,0 +1,169 @@
+"""GPU parity of the individual steps (filter, QR variants, Rayleigh-Ritz,
+residuals, Lanczos) against the oracle, called through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import filter as ofilter
+from oracle import lanczos as olanczos
+from oracle import qr as oqr
+from oracle import rr as orr
+
+from gpu_util import U32, U64, col_rel_err, phase_align, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P(gpu):
+    import paper_2603_10514_amd as P
+    return P
+
+
+def _interval(lam, L):
+    alpha, beta = lam[min(L + 4, lam.size - 2)], lam[-1]
+    return 0.5 * (alpha + beta), 0.5 * (beta - alpha), lam[0]
+
+
+FILTER_CASES = [
+    # N, ncols, cplx, degrees kind
+    (1000, 60, False, "mixed"),
+    (1000, 60, False, "const20"),
+    (1000, 61, True, "mixed"),
+    (129, 7, False, "mixed"),
+    (70, 3, True, "mixed"),
+    (517, 1, False, "one"),
+    (300, 40, True, "spread"),
+]
+
+
+def _degrees(kind, n, rng):
+    if kind == "const20":
+        return np.full(n, 20)
+    if kind == "one":
+        return np.array([1])
+    if kind == "spread":
+        return np.sort(rng.integers(1, 37, n))
+    return np.sort(np.concatenate([[1, 2, 3], rng.integers(1, 37, n - 3)]))
+
+
+@pytest.mark.parametrize("N,ncols,cplx,kind", FILTER_CASES)
+def test_filter_fp64_matches_oracle(P, gpu, N, ncols, cplx, kind):
+    print("filter case", N, ncols, cplx, kind, flush=True)
+    H, lam = synth.planted_numpy(N, "uniform" if not cplx else "dft", 3, cplx)
+    V = synth.start_block(N, ncols, 4, cplx)
+    deg = _degrees(kind, ncols, np.random.default_rng(5))
+    c, e, g = _interval(lam, ncols)
+    ref = ofilter.chebyshev_filter(H, V, deg, c, e, g)
+    out = to_host(P.chase_filter(to_dev(H, gpu), to_dev(V, gpu), deg, c, e, g))
+    # bound: each of the m steps adds about N u relative to the column scale
+    tol = 4.0 * int(deg.max()) * N * U64
+    assert col_rel_err(out, ref) <= tol
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_filter_fp32_matches_oracle(P, gpu, cplx):
+    N, ncols = 1000, 60
+    H, lam = synth.planted_numpy(N, "dft", 6, cplx)
+    V = synth.start_block(N, ncols, 7, cplx)
+    deg = _degrees("mixed", ncols, np.random.default_rng(8))
+    c, e, g = _interval(lam, ncols)
+    ref = ofilter.chebyshev_filter(H, V, deg, c, e, g)
+    out = to_host(P.chase_filter(to_dev(H, gpu), to_dev(V, gpu), deg, c, e, g,
+                                 precision=P.PREC_MIXED))
+    # FP32 storage and accumulation: a rounding error of u32 per step and per
+    # operand, accumulated over sqrt(N) terms and m steps
+    tol = 8.0 * int(deg.max()) * np.sqrt(N) * U32
+    err = col_rel_err(out, ref)
+    assert err <= tol, (err, tol)
+
+
+def planted_block(N, L, kappa, seed, cplx):
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((N, L)) + (1j * rng.standard_normal((N, L)) if cplx else 0)
+    G2 = rng.standard_normal((L, L)) + (1j * rng.standard_normal((L, L)) if cplx else 0)
+    Uo, _ = np.linalg.qr(G1)
+    Wo, _ = np.linalg.qr(G2)
+    s = np.logspace(0, -np.log10(kappa), L)
+    return np.asfortranarray((Uo * s) @ Wo.conj().T)
+
+
+QR_CASES = [
+    ("chol1", 10.0), ("chol2", 10.0), ("chol2", 1e4), ("chol2", 1e7), ("shifted", 1e7),
+    ("shifted", 1e11), ("householder", 1e11),
+]
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("variant,kappa", QR_CASES)
+def test_qr_variant_matches_oracle(P, gpu, variant, kappa, cplx):
+    N, L = 1000, 130  # several 64-wide panels, ragged last panel
+    print("qr case", variant, kappa, cplx, flush=True)
+    X = planted_block(N, L, kappa, 11, cplx)
+    Qref, failed_ref = oqr.dynamic_caqr(X, variant)
+    Xd = to_dev(X, gpu)
+    failed = P.chase_qr_factor(Xd, variant)
+    Q = to_host(Xd)
+    assert failed == failed_ref
+    orth = np.linalg.norm(Q.conj().T @ Q - np.eye(L))
+    if variant == "chol1":
+        assert orth <= 10 * L * kappa**2 * U64
+    else:
+        assert orth <= 100 * L * U64
+    # Q = X R^{-1} is unique up to column phases; it inherits kappa * u
+    diff = col_rel_err(phase_align(Q, Qref), Qref)
+    assert diff <= 100 * L * max(kappa, 1.0) * U64 * (kappa if variant == "chol1" else 1.0)
+    span = np.linalg.norm(X - Q @ (Q.conj().T @ X)) / np.linalg.norm(X)
+    assert span <= 1e-10
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_qr_fallback_to_householder(P, gpu, cplx):
+    N, L = 600, 70
+    X = planted_block(N, L, 1e17, 12, cplx)
+    for variant in ["chol2", "shifted"]:
+        Qref, failed_ref = oqr.dynamic_caqr(X, variant)
+        Xd = to_dev(X, gpu)
+        failed = P.chase_qr_factor(Xd, variant)
+        Q = to_host(Xd)
+        assert failed and failed_ref
+        assert np.linalg.norm(Q.conj().T @ Q - np.eye(L)) <= 100 * L * U64
+
+
+@pytest.mark.parametrize("N,L,cplx", [(1000, 60, False), (600, 37, True), (200, 130, False)])
+def test_rayleigh_ritz_and_residuals(P, gpu, N, L, cplx):
+    H, lam = synth.planted_numpy(N, "uniform", 13, cplx)
+    Q, _ = np.linalg.qr(synth.start_block(N, L, 14, cplx))
+    Q = np.asfortranarray(Q)
+    th_ref, V_ref, HV_ref = orr.rayleigh_ritz(H, Q)
+    Hd = to_dev(H, gpu)
+    th, V, HV = P.chase_rayleigh_ritz(Hd, to_dev(Q, gpu))
+    scale = np.max(np.abs(lam))
+    assert np.max(np.abs(th - th_ref)) <= 100 * N * U64 * scale
+    Vh = to_host(V)
+    # eigenvectors: unique up to phase for the (simple) Ritz values here
+    ov = np.abs(np.sum(Vh.conj() * V_ref, axis=0))
+    assert np.all(ov >= 1 - 1e-8)
+    # residual kernel on identical inputs: element by element
+    r_ref = orr.residual_norms(HV_ref, V_ref, th_ref)
+    r = P.chase_residuals(to_dev(HV_ref, gpu), to_dev(V_ref, gpu), th_ref)
+    assert np.max(np.abs(r - r_ref) / r_ref) <= 1e-12
+    # and on the GPU's own RR output
+    r2 = P.chase_residuals(HV, V, th)
+    assert np.max(np.abs(r2 - r_ref)) <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("N,cplx", [(1000, False), (700, True)])
+def test_lanczos_matches_oracle(P, gpu, N, cplx):
+    H, lam = synth.planted_numpy(N, "dft", 15, cplx)
+    v0 = synth.lanczos_start(N, 16, cplx)
+    a_ref, b_ref = olanczos.lanczos_tridiag(H, v0, 40)
+    bounds_ref = olanczos.lanczos_bounds(H, 60, v0, 40)
+    a, b, bounds = P.chase_lanczos(to_dev(H, gpu), to_dev(v0, gpu), 40, 60)
+    scale = np.max(np.abs(lam))
+    # Lanczos with full reorthogonalisation is forward stable here; the
+    # coefficients drift by a few ulps per step
+    assert np.max(np.abs(a - a_ref)) <= 1e-9 * scale
+    assert np.max(np.abs(b - b_ref)) <= 1e-9 * scale
+    assert np.allclose(bounds, bounds_ref, rtol=1e-8, atol=1e-9 * scale)
+    assert bounds[2] >= lam[-1]
