@@ -24,13 +24,16 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False, jobs=3):
+def build(verbose=False, jobs=3, defines=(), out=None):
     cc = hipcc()
     flags = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include",
-             "-Wno-unused-result"]
-    objdir = os.path.join(HERE, "_build")
+             "-Wno-unused-result",
+             # MFMA accumulators in arch VGPRs: no AGPR round trips per K chunk
+             "-mllvm", "--amdgpu-mfma-vgpr-form"] + ["-D" + d for d in defines]
+    lib = out or LIB
+    objdir = os.path.join(HERE, "_build", os.path.basename(lib))
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
@@ -43,12 +46,12 @@ def build(verbose=False, jobs=3):
         if len(procs) >= jobs:
             _drain(procs, verbose)
     _drain(procs, verbose)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
         "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     _run(cmd, verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def _run(cmd, verbose):

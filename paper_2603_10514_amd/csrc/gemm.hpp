@@ -52,6 +52,29 @@ template <> struct Mfma<float> {
   }
 };
 
+// Element types as the GEMM reads and writes them: T, or a native 2-vector
+// (re, im) for complex data (bit-compatible with interleaved storage).
+template <typename T, bool CPLX> struct MemT { typedef T type; };
+template <typename T> struct MemT<T, true> { typedef T __attribute__((ext_vector_type(2))) type; };
+
+template <typename T> __device__ __forceinline__ T mre(T v) { return v; }
+template <typename T> __device__ __forceinline__ T mim(T) { return (T)0; }
+__device__ __forceinline__ double mre(double __attribute__((ext_vector_type(2))) v) { return v.x; }
+__device__ __forceinline__ double mim(double __attribute__((ext_vector_type(2))) v) { return v.y; }
+__device__ __forceinline__ float mre(float __attribute__((ext_vector_type(2))) v) { return v.x; }
+__device__ __forceinline__ float mim(float __attribute__((ext_vector_type(2))) v) { return v.y; }
+
+template <typename M, typename T> __device__ __forceinline__ M mmake(T r, T i) {
+  if constexpr (sizeof(M) == sizeof(T)) {
+    return (M)r;
+  } else {
+    M v;
+    v.x = r;
+    v.y = i;
+    return v;
+  }
+}
+
 enum { EPI_AXPBY = 0, EPI_FILTER = 1 };
 
 struct GemmArgs {
@@ -75,9 +98,9 @@ struct GemmArgs {
 };
 
 template <typename T, bool CPLX, bool AT, bool CONJA, int BM, int BN, int BK, int WM, int WN,
-          int EPI, typename FT>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
-  typedef typename Elem<T, CPLX>::type E;
+          int EPI, typename FT, int MINB>
+__global__ __launch_bounds__(256, MINB) void gemm_kernel(const GemmArgs p) {
+  typedef typename MemT<T, CPLX>::type E;
   typedef typename Mfma<T>::acc Acc;
   constexpr int NT = 256;
   constexpr int NWM = BM / WM;
@@ -113,8 +136,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
     if (kend > cap) kend = cap;
   }
 
-  const E *Ag = reinterpret_cast<const E *>(p.A);
-  const E *Bg = reinterpret_cast<const E *>(p.B);
+  // global (address space 1) pointers: loads become global_load rather
+  // than flat_load, which would also count against the LDS wait counter
+  typedef const E __attribute__((address_space(1))) GE;
+  typedef E __attribute__((address_space(1))) GEw;
+  const GE *Ag = (const GE *)p.A;
+  const GE *Bg = (const GE *)p.B;
 
   Acc accR[FM][FN];
   Acc accI[FM][FN];
@@ -126,7 +153,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
       for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
 
   E ra[AE], rb[BE];
-  const E zero = make_elem<E>(0.0, 0.0);
+  const E zero = mmake<E, T>((T)0, (T)0);
 
   auto load_tiles = [&](int k0) {
 #pragma unroll
@@ -157,15 +184,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
       const int idx = tid + e * NT;
       int i, k;
       if (AT) { k = idx % BK; i = idx / BK; } else { i = idx % BM; k = idx / BM; }
-      As[buf][0][k][i] = re_of(ra[e]);
-      if constexpr (CPLX) As[buf][NP - 1][k][i] = CONJA ? -im_of(ra[e]) : im_of(ra[e]);
+      As[buf][0][k][i] = mre(ra[e]);
+      if constexpr (CPLX) As[buf][NP - 1][k][i] = CONJA ? -mim(ra[e]) : mim(ra[e]);
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
       const int idx = tid + e * NT;
       const int k = idx % BK, j = idx / BK;
-      Bs[buf][0][k][j] = re_of(rb[e]);
-      if constexpr (CPLX) Bs[buf][NP - 1][k][j] = im_of(rb[e]);
+      Bs[buf][0][k][j] = mre(rb[e]);
+      if constexpr (CPLX) Bs[buf][NP - 1][k][j] = mim(rb[e]);
     }
   };
 
@@ -218,8 +245,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
     if (j >= p.N) continue;
     const int jg = p.col0 + j;
     if (EPI == EPI_AXPBY) {
-      E *Cg = reinterpret_cast<E *>(p.C) + (int64_t)blockIdx.y * p.split_stride +
-              (int64_t)(p.ccol0 + j) * p.ldc;
+      GEw *Cg = (GEw *)p.C + (int64_t)blockIdx.y * p.split_stride +
+                (int64_t)(p.ccol0 + j) * p.ldc;
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -229,19 +256,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
           T vr = alpha * accR[a][b][r], vi = alpha * accI[a][b][r];
           if (p.beta != 0.0) {
             const E c = Cg[i];
-            vr += beta * re_of(c);
-            vi += beta * im_of(c);
+            vr += beta * mre(c);
+            vi += beta * mim(c);
           }
-          Cg[i] = make_elem<E>(vr, vi);
+          Cg[i] = mmake<E, T>(vr, vi);
         }
     } else {
-      typedef typename Elem<FT, CPLX>::type EF;
+      typedef typename MemT<FT, CPLX>::type EF;
+      typedef EF __attribute__((address_space(1))) GEF;
       const bool fin = p.deg[jg] == p.step;
       const T shift = (T)p.shift;
-      const E *Xc = Bg + (int64_t)jg * p.ldb;
-      const E *Xp = reinterpret_cast<const E *>(p.Xprev) + (int64_t)jg * p.ldp;
-      E *On = reinterpret_cast<E *>(p.Onext) + (int64_t)jg * p.ldn;
-      EF *Of = reinterpret_cast<EF *>(p.Ofinal) + (int64_t)jg * p.ldf;
+      const GE *Xc = Bg + (int64_t)jg * p.ldb;
+      const GE *Xp = (const GE *)p.Xprev + (int64_t)jg * p.ldp;
+      GEw *On = (GEw *)p.Onext + (int64_t)jg * p.ldn;
+      GEF *Of = (GEF *)p.Ofinal + (int64_t)jg * p.ldf;
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -249,17 +277,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs p) {
           const int i = m0 + wm * WM + a * 16 + Mfma<T>::row(lk, r);
           if (i >= p.M) continue;
           const E x = Xc[i];
-          T vr = alpha * (accR[a][b][r] - shift * re_of(x));
-          T vi = alpha * (accI[a][b][r] - shift * im_of(x));
+          T vr = alpha * (accR[a][b][r] - shift * mre(x));
+          T vi = alpha * (accI[a][b][r] - shift * mim(x));
           if (p.beta != 0.0) {
             const E xp = Xp[i];
-            vr += beta * re_of(xp);
-            vi += beta * im_of(xp);
+            vr += beta * mre(xp);
+            vi += beta * mim(xp);
           }
           if (fin)
-            Of[i] = make_elem<EF>((double)vr, (double)vi);
+            Of[i] = mmake<EF, FT>((FT)vr, (FT)vi);
           else
-            On[i] = make_elem<E>(vr, vi);
+            On[i] = mmake<E, T>(vr, vi);
         }
     }
   }
