@@ -7,10 +7,10 @@
  * Problem statement (Sec. 1.2, Alg. 1): given a Hermitian (complex) or
  * symmetric (real) matrix H of order N, find the nev lowest eigenpairs
  * (Lambda, Y), ascending, using a search space of l = nev + nex vectors, a
- * Chebyshev filter whose per-vector degrees are optimised (Sec. 2.3), the
- * estimate of kappa_2 of the filtered block (eq:simple-est, eq:full-est) to
+ * Chebyshev filter whose per-vector degrees are optimised (Sec. 2.2), the
+ * estimate of kappa_2 of the filtered block (estimate (1.1), estimate (1.2)) to
  * pick CholeskyQR / CholeskyQR2 / shifted CholeskyQR2 / Householder QR
- * (Alg. 3), Rayleigh-Ritz, and residual-based locking (eq:res).
+ * (Alg. 3), Rayleigh-Ritz, and residual-based locking (the residual of Sec. 2.3.1).
  *
  * Conventions for every entry point:
  *  - Matrices are column-major.  Complex matrices are interleaved
@@ -65,7 +65,7 @@ typedef enum chase_qr {
   CHASE_QR_HOUSEHOLDER = 4  /* Householder QR                                 */
 } chase_qr;
 
-/* One record per iteration of Alg. 1 (the quantities of Sec. 4.2 / 4.3). */
+/* One record per iteration of Alg. 1 (the quantities of Sec. 4.3 / 4.4). */
 typedef struct chase_iter_log {
   int32_t iter;          /* 1-based                                            */
   int32_t locked;        /* k: pairs locked before this iteration              */
@@ -75,7 +75,7 @@ typedef struct chase_iter_log {
   int32_t filter_prec;   /* chase_precision of this iteration's filter          */
   int32_t deg_min, deg_max;
   int64_t matvecs;       /* sum of this iteration's degrees                    */
-  double cond_est;       /* eq:full-est with eta = 1 (may be +inf)             */
+  double cond_est;       /* estimate (1.2) with eta = 1 (may be +inf)             */
   double c, e, gamma, lam1; /* filter centre, half-width, normalisation point,
                                lowest Ritz value (the rho_1 point)              */
   double t_filter, t_qr, t_rr, t_resid; /* seconds, device events               */
@@ -85,7 +85,7 @@ typedef struct chase_opts {
   int32_t struct_size;       /* sizeof(chase_opts); set by chase_opts_default  */
   chase_dtype dtype;
   chase_precision precision;
-  int32_t deg_opt;           /* 1: per-vector optimised degrees (Sec. 2.3)      */
+  int32_t deg_opt;           /* 1: per-vector optimised degrees (Sec. 2.2)      */
   int32_t min_deg, max_deg;  /* clamp of the optimised degrees (default 1, 36)  */
   int32_t deg_margin;        /* degrees added to the predicted one (default 2)  */
   int32_t max_iter;          /* default 25                                      */
@@ -126,8 +126,8 @@ void chase_opts_default(chase_opts *opts);
  * chase_solve: Alg. 1 end to end, synchronous.
  *   H      device, N x N, leading dimension ldh >= N, read only.
  *   nev, nex: 1 <= nev, nev + nex <= N.
- *   degree: initial filter degree (Sec. 4.2 uses 20), >= 1.
- *   tol:   residual tolerance of eq:res (> 0).
+ *   degree: initial filter degree (Sec. 4.3 uses 20), >= 1.
+ *   tol:   residual tolerance of the residual of Sec. 2.3.1 (> 0).
  *   evals  host [nev]: ascending eigenvalues (locked ones first).
  *   evecs  device, N x (nev + nex), ldv >= N: on exit columns 0..nev-1 are the
  *          eigenvectors, the rest the remaining Ritz vectors (a warm start for
@@ -168,7 +168,7 @@ void chase_handle_destroy(chase_handle *h);
  * Each runs one step of the hot path on device buffers, for testing the
  * steps one by one against a reference.  Workspace is allocated per call. */
 
-/* Chebyshev filter with per-vector degrees (Alg. 4, Sec. 2.3): column a of
+/* Chebyshev filter with per-vector degrees (Alg. 4, Sec. 2.2): column a of
  * out = p_{m_a}(H) V[:, a], p_m(x) = C_m((x-c)/e) / C_m((gamma-c)/e).
  * degrees: host int32[ncols], ascending, each >= 1.  prec MIXED runs the
  * recurrence in FP32 (H and V rounded to FP32) and writes FP64 results. */
@@ -177,7 +177,7 @@ chase_status chase_filter(chase_dtype dtype, chase_precision prec, const void *H
                           const int32_t *degrees, double c, double e, double gamma,
                           void *out, int64_t ldo, void *stream);
 
-/* ln of eq:full-est: m_next ln|rho(theta_next)| + (m_max - m_next) ln|rho(lam1)|
+/* ln of estimate (1.2): m_next ln|rho(theta_next)| + (m_max - m_next) ln|rho(lam1)|
  * (eta = 1); |rho(x)| = |t| + sqrt(t^2 - 1) for |t| = |x - c|/e > 1, else 1. */
 double chase_log_cond_estimate(double theta_next, int32_t m_next, int32_t m_max, double lam1,
                                double c, double e);
@@ -203,7 +203,7 @@ chase_status chase_rayleigh_ritz(chase_dtype dtype, const void *H, int64_t N, in
                                  const void *Q, int64_t ldq, int32_t ncols, double *ritz,
                                  void *V, int64_t ldv, void *HV, int64_t ldhv, void *stream);
 
-/* eq:res: resid[a] = ||HV[:,a] - ritz[a] V[:,a]||_2 / ||V[:,a]||_2 (host out). */
+/* the residual of Sec. 2.3.1: resid[a] = ||HV[:,a] - ritz[a] V[:,a]||_2 / ||V[:,a]||_2 (host out). */
 chase_status chase_residuals(chase_dtype dtype, const void *HV, int64_t ldhv, const void *V,
                              int64_t ldv, int64_t N, int32_t ncols, const double *ritz,
                              double *resid, void *stream);

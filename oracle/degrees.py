@@ -1,4 +1,4 @@
-"""Per-vector polynomial degrees (paper Sec. 2.3 last paragraph; Sec. 4.2).
+"""Per-vector polynomial degrees (paper Sec. 2.2 last paragraph; Sec. 4.3).
 
 Oracle module (test infrastructure only).
 

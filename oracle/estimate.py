@@ -1,5 +1,5 @@
 """Condition-number estimate of the filtered block and the QR-variant choice
-(paper eq:simple-est, eq:full-est in Sec. 1.3.1; Alg. 3; Cor. 3.5).
+(paper estimate (1.1), estimate (1.2) in Sec. 1.3.1; Alg. 3; Cor. 3.5).
 
 Oracle module (test infrastructure only).
 """
@@ -17,10 +17,10 @@ EST_LO = 20.0
 
 def log_cond_estimate(theta_next, m_next, m_max, lam1, c, e, eta=1.0):
     """ln of the estimate kappa_est = eta |rho_{k+1}|^{m_{k+1}} |rho_1|^{m_l - m_{k+1}}
-    (eq:full-est).  |rho_1| is taken at lam1 (the lowest eigenvalue estimate),
+    (estimate (1.2)).  |rho_1| is taken at lam1 (the lowest eigenvalue estimate),
     |rho_{k+1}| at theta_next (the lowest unconverged Ritz value) and m_{k+1} is
     that column's degree; m_max is the largest degree of the pass (m_l).
-    With no locked vectors and theta_next = lam1 this is eq:simple-est with
+    With no locked vectors and theta_next = lam1 this is estimate (1.1) with
     m -> m_l.  eta = 1 following the remark after Prop. 3.2.  Evaluated in log
     space so that large degrees do not overflow."""
     lr_next = math.log(rho_abs(theta_next, c, e))

@@ -1,5 +1,5 @@
 """Chebyshev filter with per-vector degrees (paper Alg. 4 and the per-vector
-stopping rule at the end of Sec. 2.3).
+stopping rule at the end of Sec. 2.2).
 
 Oracle module (test infrastructure only).
 """
@@ -12,8 +12,8 @@ def chebyshev_filter(H, V, degrees, c, e, gamma):
     """Return (p_{m_1}(H) v_1, ..., p_{m_l}(H) v_l) for the columns of V.
 
     Alg. 4: V1 = (sigma_1/e)(H - cI)V;  Vi = (2 sigma_i/e)(H - cI)V(i-1)
-    - sigma_{i-1} sigma_i V(i-2), with sigma from Sec. 2.3.  Column a stops
-    being filtered once its degree m_a is reached (Sec. 2.3, last paragraph):
+    - sigma_{i-1} sigma_i V(i-2), with sigma from Sec. 2.2.  Column a stops
+    being filtered once its degree m_a is reached (Sec. 2.2, last paragraph):
     its output is the iterate of step m_a.  The columns may come in any
     order; degrees must be >= 1.  ``gamma`` is the point where p(gamma) = 1
     (the estimate of the lowest eigenvalue).

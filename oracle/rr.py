@@ -1,4 +1,4 @@
-"""Rayleigh-Ritz projection and residual norms (paper Alg. 1, eq:res).
+"""Rayleigh-Ritz projection and residual norms (paper Alg. 1, the residual of Sec. 2.3.1).
 
 Oracle module (test infrastructure only).
 """
@@ -18,6 +18,6 @@ def rayleigh_ritz(H, Q):
 
 
 def residual_norms(HV, V, theta):
-    """eq:res: ||A v_a - theta_a v_a||_2 / ||v_a||_2 for every column a."""
+    """the residual of Sec. 2.3.1: ||A v_a - theta_a v_a||_2 / ||v_a||_2 for every column a."""
     R = HV - V * theta[np.newaxis, :]
     return np.linalg.norm(R, axis=0) / np.linalg.norm(V, axis=0)

@@ -1,15 +1,15 @@
 """ChASE driver loop (paper Alg. 1) with the dynamic QR choice (Alg. 3)
-driven by the condition-number estimate (eq:full-est).
+driven by the condition-number estimate (estimate (1.2)).
 
 Oracle module (test infrastructure only).
 
 Readings of points the paper leaves open (each is listed in the design notes):
   * filter interval: damp [alpha, beta] = [lambda_l estimate, upper bound],
-    normalise at gamma = lambda_1 estimate (Sec. 2.2-2.3, Fig. 1; the centre
+    normalise at gamma = lambda_1 estimate (Sec. 2.1-2.2, Fig. 1; the centre
     and half-width printed in Alg. 4 give sigma_1 = -1 and are not used);
   * first iteration: no Ritz values yet, so theta_{k+1} = gamma;
   * step 0: the start block is orthonormalised with CholeskyQR2 before the
-    first filter (Sec. 4.2 calls the QR of the random block "step 0");
+    first filter (Sec. 4.3 calls the QR of the random block "step 0");
   * QR always on [Y V] (Sec. 1.2), then the locked columns are restored
     exactly; Rayleigh-Ritz acts on the unlocked part only;
   * locking: the contiguous prefix (ascending Ritz order, index < nev) whose
@@ -18,8 +18,8 @@ Readings of points the paper leaves open (each is listed in the design notes):
     beta fixed; the filter is normalised (p(gamma) = 1) at the lowest
     unconverged Ritz value gamma = theta_{k+1}, while |rho_1| of the estimate
     is taken at the lowest Ritz value overall (locked or not).  Normalising at
-    theta_{k+1} is what makes eq:full-est (|rho_{k+1}|^m without degree
-    optimisation, Sec. 4.2) an upper bound of kappa_2([Y, filtered]): with the
+    theta_{k+1} is what makes estimate (1.2) (|rho_{k+1}|^m without degree
+    optimisation, Sec. 4.3) an upper bound of kappa_2([Y, filtered]): with the
     normalisation at the lowest locked value the filtered columns shrink by
     (|rho_{k+1}|/|rho_1|)^m against the unit-norm locked ones and kappa_2
     grows to about |rho_1|^m;
@@ -97,7 +97,7 @@ def chase_solve(H, nev, nex, deg=20, tol=1e-10, *, V0, bounds=None,
         Xin = Vbuf[:, k:][:, order]
         filt = chebyshev_filter(H, Xin, m[order], c, e, gamma)
         matvecs += int(m.sum())
-        # estimate (eq:full-est); theta_{k+1} is the lowest unconverged Ritz
+        # estimate (estimate (1.2)); theta_{k+1} is the lowest unconverged Ritz
         # value and m[0] its degree (columns are in Ritz order before sorting)
         th_next = gamma if theta_act is None else float(theta_act[0])
         est = cond_estimate(th_next, int(m[0]), int(m.max()), lam1, c, e)

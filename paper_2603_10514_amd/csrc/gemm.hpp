@@ -27,7 +27,7 @@
 //  EPI_FILTER  one step of the sigma-scaled Chebyshev recurrence (Alg. 4):
 //              out = alpha * (acc - shift * Xcur) + beta * Xprev, where Xcur is
 //              B itself (K == M); column j goes to Ofinal when deg[j] == step
-//              (its last step, Sec. 2.3) and to Onext otherwise.
+//              (its last step, Sec. 2.2) and to Onext otherwise.
 #pragma once
 #include "common.hpp"
 

@@ -20,15 +20,15 @@ namespace chase {
 static const double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 
 // ------------------------------------------------------------ host logic --
-// |rho| of x for the interval [c - e, c + e] (eq:rho, convergence ratio of
-// Sec. 2.3): |t| + sqrt(t^2 - 1) outside, 1 inside.
+// |rho| of x for the interval [c - e, c + e] (the interval map of Sec. 2.1, convergence ratio of
+// Sec. 2.2): |t| + sqrt(t^2 - 1) outside, 1 inside.
 double rho_abs(double x, double c, double e) {
   const double t = (x - c) / e;
   if (std::fabs(t) <= 1.0) return 1.0;
   return std::fabs(t) + std::sqrt(t * t - 1.0);
 }
 
-// eq:full-est with eta = 1, in log space.
+// estimate (1.2) with eta = 1, in log space.
 double log_cond_estimate(double theta_next, int m_next, int m_max, double lam1, double c,
                          double e) {
   return m_next * std::log(rho_abs(theta_next, c, e)) +
@@ -43,7 +43,7 @@ chase_qr select_qr(double est, double hi, double lo) {
 }
 
 // Per-vector degree: enough steps for the residual to fall from r to tol at
-// the rate 1/|rho(theta)| per step (Sec. 2.3), plus a margin.
+// the rate 1/|rho(theta)| per step (Sec. 2.2), plus a margin.
 void degrees(const double *theta, const double *resid, int n, double tol, double c, double e,
              int min_deg, int max_deg, int margin, int *out) {
   for (int a = 0; a < n; ++a) {
@@ -683,7 +683,7 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     int mmax = 0, mmin = 1 << 30;
     for (int a = 0; a < Lp; ++a) { mv += m[a]; mmax = std::max(mmax, m[a]); mmin = std::min(mmin, m[a]); }
     inf.matvecs += mv;
-    // eq:full-est: theta_{k+1} = lowest unconverged Ritz value, m[0] its degree
+    // estimate (1.2): theta_{k+1} = lowest unconverged Ritz value, m[0] its degree
     const double th_next = theta_act.empty() ? gamma : theta_act[0];
     const double lest = log_cond_estimate(th_next, m[0], mmax, lam1, cc, e);
     const double est = lest < 709.0 ? std::exp(lest) : INFINITY;

@@ -1,5 +1,5 @@
 """Pins of oracle/chebyshev.py against closed forms of the Chebyshev
-polynomials (paper Sec. 2.2-2.3)."""
+polynomials (paper Sec. 2.1-2.2)."""
 import math
 
 import numpy as np
@@ -37,7 +37,7 @@ def test_integer_values_at_two():
 @pytest.mark.parametrize("t", [1.01, 1.5, 2.0, 7.3, -1.2, -4.0])
 @pytest.mark.parametrize("m", [1, 2, 5, 13, 36])
 def test_rho_asymptotic_identity(t, m):
-    # eq:polyas: C_m(t) = (|rho|^m + |rho|^-m)/2 for |t| > 1 (|C_m|, sign by parity)
+    # the rho form of C_m in Sec. 2.1: C_m(t) = (|rho|^m + |rho|^-m)/2 for |t| > 1 (|C_m|, sign by parity)
     rho = ch.rho_abs(t, 0.0, 1.0)
     assert rho > 1.0
     lhs = abs(ch.cheb_closed(m, t))
@@ -58,7 +58,7 @@ def test_rho_golden_ratio():
 
 @pytest.mark.parametrize("c,e,gamma", [(0.0, 1.0, -2.0), (0.063, 0.936, -0.999), (24.5, 25.5, -2.0), (500.0, 500.5, -1.0)])
 def test_sigma_is_ratio_of_polynomials(c, e, gamma):
-    # Sec. 2.3: sigma_{m+1} = eta_m / eta_{m+1}, eta_m = C_m((gamma-c)/e)
+    # Sec. 2.2: sigma_{m+1} = eta_m / eta_{m+1}, eta_m = C_m((gamma-c)/e)
     tg = (gamma - c) / e
     s = ch.sigma_sequence(30, c, e, gamma)
     for m in range(1, 31):
@@ -78,7 +78,7 @@ def test_scaled_recurrence_matches_closed_form(m):
 
 
 def test_filter_optimality_bound():
-    # inside [alpha, beta] |p_m| <= 1/|C_m(t_gamma)| (Thm. in Sec. 2.2)
+    # inside [alpha, beta] |p_m| <= 1/|C_m(t_gamma)| (Thm. in Sec. 2.1)
     c, e, gamma, m = 0.0, 1.0, -1.3, 12
     bound = 1.0 / abs(ch.cheb_closed(m, (gamma - c) / e))
     for x in np.linspace(-1, 1, 101):

@@ -1,4 +1,4 @@
-"""Pins of oracle/estimate.py (eq:simple-est, eq:full-est, Alg. 3)."""
+"""Pins of oracle/estimate.py (estimate (1.1), estimate (1.2), Alg. 3)."""
 import json
 import math
 import os
@@ -30,7 +30,7 @@ def test_hand_evaluated_full_estimate():
 
 @pytest.mark.parametrize("m_next,m_max", [(1, 20), (20, 20), (7, 36)])
 def test_full_reduces_to_simple_without_locking(m_next, m_max):
-    # eq:full-est with theta_{k+1} = lambda_1 (nothing locked) is eq:simple-est with m -> m_l
+    # estimate (1.2) with theta_{k+1} = lambda_1 (nothing locked) is estimate (1.1) with m -> m_l
     c, e, g = 0.063, 0.936, -0.999
     full = est.cond_estimate(g, m_next, m_max, g, c, e)
     simple = est.cond_estimate(g, m_max, m_max, g, c, e)
@@ -38,7 +38,7 @@ def test_full_reduces_to_simple_without_locking(m_next, m_max):
 
 
 def test_no_opt_reduces_to_single_ratio():
-    # fixed degree: the estimate is |rho_{k+1}|^m (Sec. 4.2)
+    # fixed degree: the estimate is |rho_{k+1}|^m (Sec. 4.3)
     c, e, g, th, m = 0.0, 1.0, -2.0, -1.5, 20
     assert est.cond_estimate(th, m, m, g, c, e) == pytest.approx(PHI ** (2 * m), rel=1e-12)
 
@@ -68,7 +68,7 @@ def test_variant_thresholds_from_paper():
 
 @pytest.mark.parametrize("deg_opt", [False, True])
 def test_estimate_bounds_exact_condition_number(deg_opt):
-    """Empirical property reported in Sec. 4.2: the estimate stays above the
+    """Empirical property reported in Sec. 4.3: the estimate stays above the
     exact kappa_2 (by SVD) of [Y, filtered] at every iteration."""
     N, nev, nex = 400, 16, 10
     H, lam = synth.planted_numpy(N, "uniform", 21)

@@ -1,6 +1,6 @@
 """Pins of oracle/filter.py: on a planted H = Q diag(lambda) Q^H the filtered
 block has the closed form Q diag(p_{m_a}(lambda)) Q^H v_a column by column
-(eq-2-2-1), computed here from cos/cosh without the recurrence."""
+(the spectral form of p(A)V in Sec. 2.3), computed here from cos/cosh without the recurrence."""
 import numpy as np
 import pytest
 
