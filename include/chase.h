@@ -76,6 +76,7 @@ typedef struct chase_iter_log {
   int32_t deg_min, deg_max;
   int64_t matvecs;       /* sum of this iteration's degrees                    */
   double cond_est;       /* estimate (1.2) with eta = 1 (may be +inf)             */
+  double cond_exact;     /* value returned by opts->block_cb, else NaN          */
   double c, e, gamma, lam1; /* filter centre, half-width, normalisation point,
                                lowest Ritz value (the rho_1 point)              */
   double t_filter, t_qr, t_rr, t_resid; /* seconds, device events               */
@@ -105,6 +106,15 @@ typedef struct chase_opts {
   void *stream;              /* hipStream_t or NULL                              */
   void (*log_cb)(const chase_iter_log *rec, void *user);
   void *log_user;
+  /* Diagnostic hook (Sec. 4.3 compares the estimate with the exact kappa_2):
+   * called once per iteration, after the filter and before the QR, with the
+   * device block [Y | filtered] (N x ncols, column-major, leading dimension
+   * ld, complex interleaved for COMPLEX128) after the stream has been
+   * synchronised.  The block must not be modified.  The value returned is
+   * stored as cond_exact in that iteration's log record (NaN if none). */
+  double (*block_cb)(const void *X, int64_t N, int64_t ld, int32_t ncols, int32_t iter,
+                     void *user);
+  void *block_user;
 } chase_opts;
 
 typedef struct chase_info {
@@ -115,6 +125,8 @@ typedef struct chase_info {
   int32_t filter_fp32_iters; /* iterations whose filter ran in FP32            */
   double t_total, t_filter, t_qr, t_rr, t_resid, t_lanczos; /* seconds          */
   double lambda_1, lambda_l, lambda_max; /* bounds used by the first filter     */
+  int64_t matvecs_fp32;      /* part of matvecs filtered in FP32                */
+  double t_filter_fp32;      /* part of t_filter spent in FP32 filter steps     */
 } chase_info;
 
 /* Defaults: dtype REAL64, FP64, deg_opt 1, degrees [1, 36], margin 2,

@@ -35,13 +35,16 @@ class ChaseIterLog(ctypes.Structure):
                 ("chol_failed", ctypes.c_int32), ("filter_prec", ctypes.c_int32),
                 ("deg_min", ctypes.c_int32), ("deg_max", ctypes.c_int32),
                 ("matvecs", ctypes.c_int64), ("cond_est", ctypes.c_double),
-                ("c", ctypes.c_double), ("e", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("cond_exact", ctypes.c_double), ("c", ctypes.c_double),
+                ("e", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("lam1", ctypes.c_double), ("t_filter", ctypes.c_double),
                 ("t_qr", ctypes.c_double), ("t_rr", ctypes.c_double),
                 ("t_resid", ctypes.c_double)]
 
 
 LOG_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(ChaseIterLog), ctypes.c_void_p)
+BLOCK_CB = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p)
 
 
 class ChaseOpts(ctypes.Structure):
@@ -56,7 +59,8 @@ class ChaseOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("lanczos_steps", ctypes.c_int32),
                 ("lanczos_v0", ctypes.c_void_p), ("inject_chol_fail_iter", ctypes.c_int32),
                 ("mixed_switch", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("log_cb", LOG_CB), ("log_user", ctypes.c_void_p)]
+                ("log_cb", LOG_CB), ("log_user", ctypes.c_void_p),
+                ("block_cb", BLOCK_CB), ("block_user", ctypes.c_void_p)]
 
 
 class ChaseInfo(ctypes.Structure):
@@ -66,7 +70,8 @@ class ChaseInfo(ctypes.Structure):
                 ("t_filter", ctypes.c_double), ("t_qr", ctypes.c_double),
                 ("t_rr", ctypes.c_double), ("t_resid", ctypes.c_double),
                 ("t_lanczos", ctypes.c_double), ("lambda_1", ctypes.c_double),
-                ("lambda_l", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+                ("lambda_l", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("matvecs_fp32", ctypes.c_int64), ("t_filter_fp32", ctypes.c_double)]
 
 
 _p = ctypes.c_void_p
@@ -187,11 +192,40 @@ def _log_dict(rec):
 
 
 # ----------------------------------------------------------- solve --------
-def chase_solve(H, nev, nex, degree=20, tol=1e-10, evecs=None, opts=None, stream=None, **kw):
+def exact_cond_host(Xptr, N, ld, ncols, cplx):
+    """kappa_2 of a device block by an SVD of its host copy (diagnostic)."""
+    import torch
+    dt = torch.complex128 if cplx else torch.float64
+    es = 16 if cplx else 8
+    host = torch.empty((ncols, ld), dtype=dt)
+    rc = _memcpy_d2h(host.data_ptr(), Xptr, es * ld * ncols)
+    if rc != 0:
+        return float("nan")
+    A = host.numpy().T[:N, :]
+    sv = np.linalg.svd(A, compute_uv=False)
+    return float(sv[0] / sv[-1]) if sv[-1] > 0 else float("inf")
+
+
+_HIP = None
+
+
+def _memcpy_d2h(dst, src, nbytes):
+    """hipMemcpy device -> host (the diagnostic copy of exact_cond_host)."""
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.restype = ctypes.c_int
+        _HIP.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return _HIP.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 2)
+
+
+def chase_solve(H, nev, nex, degree=20, tol=1e-10, evecs=None, opts=None, stream=None,
+                exact_cond=False, **kw):
     """Alg. 1 on the device matrix H.  Returns a dict with status, evals and
     resid (numpy), evecs (the N x (nev+nex) column-major device tensor), info
     and the per-iteration log.  Keyword arguments override chase_opts fields;
-    pass evecs with warm_start=1 to start from a given block."""
+    pass evecs with warm_start=1 to start from a given block.  exact_cond adds
+    kappa_2 of [Y, filtered] (SVD of a host copy) to every log record."""
     import torch
     N = H.shape[0]
     L = nev + nex
@@ -212,6 +246,9 @@ def chase_solve(H, nev, nex, degree=20, tol=1e-10, evecs=None, opts=None, stream
 
     cb = LOG_CB(_cb)
     o.log_cb = cb
+    cplx = o.dtype == COMPLEX128
+    bcb = BLOCK_CB(lambda X, n, ld, nc, it, user: exact_cond_host(X, n, ld, nc, cplx))
+    o.block_cb = bcb if exact_cond else BLOCK_CB()
     o.stream = _stream_ptr(stream).value
     evals = np.zeros(nev)
     resid = np.zeros(nev)
@@ -220,6 +257,7 @@ def chase_solve(H, nev, nex, degree=20, tol=1e-10, evecs=None, opts=None, stream
                          evals.ctypes.data_as(_dp), vp, ldv, resid.ctypes.data_as(_dp),
                          ctypes.byref(info))
     o.log_cb = LOG_CB()
+    o.block_cb = BLOCK_CB()
     _check(st, "chase_solve", (CHASE_OK, CHASE_NOT_CONVERGED))
     return dict(status=st, evals=evals, resid=resid, evecs=evecs, info=_info_dict(info), log=logs)
 
@@ -330,6 +368,7 @@ class Handle:
         vp, ldv = _colmajor(evecs, "evecs")
         opts.dtype = _dtype_code(H)
         opts.log_cb = LOG_CB()
+        opts.block_cb = BLOCK_CB()
         opts.stream = None
         evals = np.zeros(nev)
         resid = np.zeros(nev)

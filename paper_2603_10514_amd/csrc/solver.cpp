@@ -691,6 +691,11 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
                                                      : o.qr_policy;
     // [Y | filtered]
     if (k > 0) copy_cols(cplx, evecs, ldv, w.Xq, N, (int)N, k, s);
+    double kappa = NAN;
+    if (o.block_cb) {
+      CHASE_HIP(hipStreamSynchronize(s));
+      kappa = o.block_cb(w.Xq, N, N, L, it, o.block_user);
+    }
     QrOut q = qr(c, cplx, w.Xq, w.B1, N, N, L, variant, o.inject_chol_fail_iter == it);
     CHASE_HIP(hipEventRecord(c.ev[2], s));
     void *Q2 = (char *)q.Q + es * (size_t)k * N;
@@ -709,6 +714,7 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     rec.t_rr = elapsed(c.ev[2], c.ev[3]);
     rec.t_resid = elapsed(c.ev[3], c.ev[4]);
     inf.t_filter += rec.t_filter; inf.t_qr += rec.t_qr; inf.t_rr += rec.t_rr;
+    if (f32) { inf.t_filter_fp32 += rec.t_filter; inf.matvecs_fp32 += mv; }
     inf.t_resid += rec.t_resid;
     std::vector<double> th(w.h_theta, w.h_theta + Lp), rr(w.h_resid, w.h_resid + Lp);
     int j = k;
@@ -718,6 +724,7 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     rec.iter = it; rec.locked = k; rec.newly_locked = newly; rec.qr_variant = q.ran;
     rec.chol_failed = q.failed; rec.filter_prec = f32 ? CHASE_PREC_MIXED : CHASE_PREC_FP64;
     rec.deg_min = mmin; rec.deg_max = mmax; rec.matvecs = mv; rec.cond_est = est;
+    rec.cond_exact = kappa;
     rec.c = cc; rec.e = e; rec.gamma = gamma; rec.lam1 = lam1;
     if (o.log_cb) o.log_cb(&rec, o.log_user);
     k = j;

@@ -133,3 +133,59 @@ def test_random_start_block_default_path(P, gpu):
     out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, seed=5)
     assert out["status"] == P.CHASE_OK
     assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10
+
+
+@pytest.mark.parametrize("cplx,family", [(False, "uniform"), (True, "dft")])
+def test_mixed_precision_matches_fp64_oracle(P, gpu, cplx, family):
+    """FP32 filter (FP64 everything else) reaches the FP64 oracle's
+    eigenvalues to 1e-10 relative and residuals below tol."""
+    N, nev, nex = (1000, 40, 20) if not cplx else (800, 40, 16)
+    H, lam = synth.planted_numpy(N, family, 21, cplx)
+    ref, out = _run(P, gpu, H, lam, nev, nex, cplx, 22, precision=P.PREC_MIXED)
+    assert out["status"] == P.CHASE_OK
+    scale = np.max(np.abs(lam))
+    assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10 * scale
+    assert np.all(out["resid"] < 1e-10)
+    assert out["info"]["filter_fp32_iters"] >= 1
+    assert out["log"][0]["filter_prec"] == P.PREC_MIXED
+    assert out["info"]["matvecs_fp32"] > 0
+
+
+def test_exact_condition_number_logged(P, gpu):
+    """Sec. 4.3: the estimate against the exact kappa_2 of [Y, filtered],
+    per iteration, on the GPU and in the oracle."""
+    N, nev, nex = 600, 24, 12
+    H, lam = synth.planted_numpy(N, "uniform", 23)
+    V0 = synth.start_block(N, nev + nex, 24)
+    b = (lam[0], lam[nev + nex - 1], lam[-1])
+    ref = osolver.chase_solve(H, nev, nex, 20, 1e-10, V0=V0, bounds=b, exact_cond=True)
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=to_dev(V0, gpu), warm_start=1,
+                        have_bounds=1, lambda_1=b[0], lambda_l=b[1], lambda_max=b[2],
+                        exact_cond=True)
+    assert len(out["log"]) == len(ref.log)
+    for g, o in zip(out["log"], ref.log):
+        assert g["cond_exact"] == pytest.approx(o["cond_exact"], rel=1e-3)
+        assert g["cond_est"] >= g["cond_exact"]
+
+
+@pytest.mark.parametrize("degree", [6, 40, 70, 100])
+def test_fixed_degree_sweep_exercises_alg3(P, gpu, degree):
+    """Without degree optimisation the first iteration's estimate grows with
+    the degree and walks Alg. 3 through CholeskyQR, CholeskyQR2 and the
+    shifted branch (stress spectrum, scaled down to N = 1500)."""
+    N, nev, nex = 1500, 60, 30
+    H, lam = synth.planted_numpy(N, "stress", 25, n_low=60)
+    V0 = synth.start_block(N, nev + nex, 26)
+    b = (lam[0], lam[nev + nex - 1], lam[-1])
+    ref = osolver.chase_solve(H, nev, nex, degree, 1e-10, V0=V0, bounds=b, deg_opt=False,
+                              max_iter=3, exact_cond=True)
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, degree, 1e-10, evecs=to_dev(V0, gpu),
+                        warm_start=1, have_bounds=1, lambda_1=b[0], lambda_l=b[1],
+                        lambda_max=b[2], deg_opt=0, max_iter=3, exact_cond=True)
+    g, o = out["log"][0], ref.log[0]
+    assert g["variant"] == o["variant"]
+    assert g["cond_est"] == pytest.approx(o["cond_est"], rel=1e-9)
+    assert g["cond_est"] >= g["cond_exact"]
+    assert g["cond_exact"] == pytest.approx(o["cond_exact"], rel=1e-2)
+    expect = "chol1" if o["cond_est"] < 20 else ("chol2" if o["cond_est"] <= 1e8 else "shifted")
+    assert g["variant"] == expect
