@@ -95,7 +95,51 @@ struct GemmArgs {
   void *Ofinal; int64_t ldf;
   const int *deg; int step;
   const int *flag;       // non-null and *flag != 0: the launch does nothing
+  // remainder split (set by the launcher): this launch covers logical tiles
+  // [tile0, tile0 + ntiles) (ntiles == 0: all); with Pk set, every (tile,
+  // split) writes its raw BM x BN partial sum to Pk and gemm_reduce_kernel
+  // applies the epilogue.
+  int tile0, ntiles;
+  void *Pk;
+  void *tail_ws; size_t tail_ws_bytes;  // scratch the launcher may use for Pk
 };
+
+// The epilogue of one output element (row i, column j of this launch).
+template <typename T, bool CPLX, int EPI, typename FT>
+__device__ __forceinline__ void epilogue_store(const GemmArgs &p, int i, int j, T ar, T ai,
+                                               int64_t split_off) {
+  typedef typename MemT<T, CPLX>::type E;
+  typedef const E __attribute__((address_space(1))) GE;
+  typedef E __attribute__((address_space(1))) GEw;
+  const T alpha = (T)p.alpha, beta = (T)p.beta;
+  if constexpr (EPI == EPI_AXPBY) {
+    GEw *Cg = (GEw *)p.C + split_off + (int64_t)(p.ccol0 + j) * p.ldc;
+    T vr = alpha * ar, vi = alpha * ai;
+    if (p.beta != 0.0) {
+      const E c = Cg[i];
+      vr += beta * mre(c);
+      vi += beta * mim(c);
+    }
+    Cg[i] = mmake<E, T>(vr, vi);
+  } else {
+    typedef typename MemT<FT, CPLX>::type EF;
+    typedef EF __attribute__((address_space(1))) GEF;
+    const int jg = p.col0 + j;
+    const T shift = (T)p.shift;
+    const E x = ((const GE *)p.B)[(int64_t)jg * p.ldb + i];
+    T vr = alpha * (ar - shift * mre(x));
+    T vi = alpha * (ai - shift * mim(x));
+    if (p.beta != 0.0) {
+      const E xp = ((const GE *)p.Xprev)[(int64_t)jg * p.ldp + i];
+      vr += beta * mre(xp);
+      vi += beta * mim(xp);
+    }
+    if (p.deg[jg] == p.step)
+      ((GEF *)p.Ofinal)[(int64_t)jg * p.ldf + i] = mmake<EF, FT>((FT)vr, (FT)vi);
+    else
+      ((GEw *)p.Onext)[(int64_t)jg * p.ldn + i] = mmake<E, T>(vr, vi);
+  }
+}
 
 template <typename T, bool CPLX, bool AT, bool CONJA, int BM, int BN, int BK, int WM, int WN,
           int EPI, typename FT, int MINB>
@@ -118,12 +162,12 @@ __global__ __launch_bounds__(256, MINB) void gemm_kernel(const GemmArgs p) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % NWM, wn = wave / NWM;
   const int nbm = (p.M + BM - 1) / BM, nbn = (p.N + BN - 1) / BN;
-  const int nb = nbm * nbn;
+  const int nb = p.ntiles > 0 ? p.ntiles : nbm * nbn;
   // XCD-aware remap of the hardware block id (bijective on [0, nb)).
   const int hb = blockIdx.x;
   const int xcd = hb & 7, q = hb >> 3;
   const int per = nb >> 3, rem = nb & 7;
-  const int logical = xcd * per + (xcd < rem ? xcd : rem) + q;
+  const int logical = p.tile0 + xcd * per + (xcd < rem ? xcd : rem) + q;
   const int bm = logical / nbn, bn = logical % nbn;
   const int m0 = bm * BM, n0 = bn * BN;
   if (p.tri && m0 > n0 + BN - 1) return;
@@ -238,59 +282,61 @@ __global__ __launch_bounds__(256, MINB) void gemm_kernel(const GemmArgs p) {
   }
 
   // ---------------------------------------------------------- epilogue --
-  const T alpha = (T)p.alpha, beta = (T)p.beta;
+  if (p.Pk != nullptr) {  // raw partial tile of one K split
+    typedef E __attribute__((address_space(1))) GEw;
+    GEw *Pt = (GEw *)p.Pk + ((int64_t)(logical - p.tile0) * gridDim.y + blockIdx.y) * (BM * BN);
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = wm * WM + a * 16 + Mfma<T>::row(lk, r);
+          const int jj = wn * WN + b * 16 + lr;
+          Pt[jj * BM + ii] = mmake<E, T>(accR[a][b][r], accI[a][b][r]);
+        }
+    return;
+  }
+  const int64_t split_off = (int64_t)blockIdx.y * p.split_stride;
 #pragma unroll
   for (int b = 0; b < FN; ++b) {
     const int j = n0 + wn * WN + b * 16 + lr;
     if (j >= p.N) continue;
-    const int jg = p.col0 + j;
-    if (EPI == EPI_AXPBY) {
-      GEw *Cg = (GEw *)p.C + (int64_t)blockIdx.y * p.split_stride +
-                (int64_t)(p.ccol0 + j) * p.ldc;
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = m0 + wm * WM + a * 16 + Mfma<T>::row(lk, r);
-          if (i >= p.M) continue;
-          T vr = alpha * accR[a][b][r], vi = alpha * accI[a][b][r];
-          if (p.beta != 0.0) {
-            const E c = Cg[i];
-            vr += beta * mre(c);
-            vi += beta * mim(c);
-          }
-          Cg[i] = mmake<E, T>(vr, vi);
-        }
-    } else {
-      typedef typename MemT<FT, CPLX>::type EF;
-      typedef EF __attribute__((address_space(1))) GEF;
-      const bool fin = p.deg[jg] == p.step;
-      const T shift = (T)p.shift;
-      const GE *Xc = Bg + (int64_t)jg * p.ldb;
-      const GE *Xp = (const GE *)p.Xprev + (int64_t)jg * p.ldp;
-      GEw *On = (GEw *)p.Onext + (int64_t)jg * p.ldn;
-      GEF *Of = (GEF *)p.Ofinal + (int64_t)jg * p.ldf;
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = m0 + wm * WM + a * 16 + Mfma<T>::row(lk, r);
-          if (i >= p.M) continue;
-          const E x = Xc[i];
-          T vr = alpha * (accR[a][b][r] - shift * mre(x));
-          T vi = alpha * (accI[a][b][r] - shift * mim(x));
-          if (p.beta != 0.0) {
-            const E xp = Xp[i];
-            vr += beta * mre(xp);
-            vi += beta * mim(xp);
-          }
-          if (fin)
-            Of[i] = mmake<EF, FT>((FT)vr, (FT)vi);
-          else
-            On[i] = mmake<E, T>(vr, vi);
-        }
-    }
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm * WM + a * 16 + Mfma<T>::row(lk, r);
+        if (i >= p.M) continue;
+        epilogue_store<T, CPLX, EPI, FT>(p, i, j, accR[a][b][r], accI[a][b][r], split_off);
+      }
   }
+}
+
+// Sums the S partial tiles of the remainder tiles in a fixed order and
+// applies the epilogue (deterministic).  One thread per tile element.
+template <typename T, bool CPLX, int BM, int BN, int EPI, typename FT>
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(const GemmArgs p, int S) {
+  typedef typename MemT<T, CPLX>::type E;
+  typedef const E __attribute__((address_space(1))) GE;
+  if (p.flag != nullptr && *p.flag != 0) return;  // same skip rule as the GEMM
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int tl = (int)(e / (BM * BN));
+  const int w = (int)(e % (BM * BN));
+  if (tl >= p.ntiles) return;
+  const int ii = w % BM, jj = w / BM;
+  const int nbn = (p.N + BN - 1) / BN;
+  const int logical = p.tile0 + tl;
+  const int i = (logical / nbn) * BM + ii, j = (logical % nbn) * BN + jj;
+  if (i >= p.M || j >= p.N) return;
+  const GE *P = (const GE *)p.Pk + (int64_t)tl * S * (BM * BN) + w;
+  T sr = 0, si = 0;
+  for (int q = 0; q < S; ++q) {
+    const E v = P[(int64_t)q * (BM * BN)];
+    sr += mre(v);
+    si += mim(v);
+  }
+  epilogue_store<T, CPLX, EPI, FT>(p, i, j, sr, si, 0);
 }
 
 }  // namespace chase

@@ -1,5 +1,6 @@
 // gfx950 kernels of the solver other than the GEMM core, the GEMM
 // instantiations, and their launchers.
+#include <algorithm>
 #include <cmath>
 
 #include "gemm.hpp"
@@ -392,6 +393,18 @@ void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int nelem
 constexpr int kBK = 16;
 int gemm_bk() { return kBK; }
 
+// Blocks of one launch that run at once (occupancy x compute units).
+template <typename K> static int resident_blocks(K kernel) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return ncu * per;
+}
+
 template <typename T, bool CPLX, bool AT, int EPI, typename FT, int SHAPE>
 static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   constexpr int BM = SHAPE == GEMM_BIG ? 128 : 64;
@@ -399,15 +412,46 @@ static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int BK = SHAPE == GEMM_BIG ? (CPLX ? CHASE_BIG_BK_CPLX : CHASE_BIG_BK_REAL) : kBK;
   constexpr int MINB = 1;
+  static_assert(kBK % BK == 0, "split granularity");
+  auto kernel = gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BK, WM, WN, EPI, FT, MINB>;
   const int nbm = (a.M + BM - 1) / BM, nbn = (a.N + BN - 1) / BN;
   if (nbm <= 0 || nbn <= 0) return;
   if (splits < 1) splits = 1;
-  // split ranges are multiples of kBK, hence of BK as well (BK divides kBK)
-  static_assert(kBK % BK == 0, "split granularity");
   if (a.k_per_split <= 0) a.k_per_split = ((a.K + kBK - 1) / kBK) * kBK;
-  dim3 grid((unsigned)(nbm * nbn), (unsigned)splits);
-  hipLaunchKernelGGL((gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BK, WM, WN, EPI, FT, MINB>),
-                     grid, dim3(256), 0, s, a);
+  const int T_ = nbm * nbn;
+  a.tile0 = 0;
+  a.ntiles = 0;
+  a.Pk = nullptr;
+  // Remainder split: the tiles beyond the last full wave of resident blocks
+  // are split along K across the idle slots of that wave; their partial sums
+  // go to the scratch and a reduce kernel applies the epilogue.
+  if (SHAPE == GEMM_BIG && splits == 1 && !a.tri && a.tail_ws != nullptr) {
+    static const int C = resident_blocks(kernel);
+    const size_t es = sizeof(T) * (CPLX ? 2 : 1);
+    const int full = C > 0 ? (T_ / C) * C : T_;
+    const int R = T_ - full;
+    int S = R > 0 ? std::min(C / R, 8) : 0;
+    S = std::min(S, a.K / (2 * kBK));
+    if (R > 0 && S >= 2 && (size_t)R * S * BM * BN * es <= a.tail_ws_bytes) {
+      if (full > 0) {
+        GemmArgs b = a;
+        b.ntiles = full;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)full, 1), dim3(256), 0, s, b);
+      }
+      GemmArgs b = a;
+      b.tile0 = full;
+      b.ntiles = R;
+      b.Pk = a.tail_ws;
+      b.k_per_split = ((a.K + S - 1) / S + kBK - 1) / kBK * kBK;
+      hipLaunchKernelGGL(kernel, dim3((unsigned)R, (unsigned)S), dim3(256), 0, s, b);
+      const int64_t elems = (int64_t)R * BM * BN;
+      hipLaunchKernelGGL((gemm_reduce_kernel<T, CPLX, BM, BN, EPI, FT>),
+                         dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, b, S);
+      return;
+    }
+  }
+  dim3 grid((unsigned)T_, (unsigned)splits);
+  hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, a);
 }
 
 void gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,

@@ -146,6 +146,9 @@ void lanczos_bounds_from_tridiag(const std::vector<double> &alpha, const std::ve
 
 // --------------------------------------------------------------- workspace --
 static inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+// Scratch of the big GEMMs' remainder split: at most one wave of resident
+// blocks (<= 1024) x one 128 x 64 complex (or 128 x 128 real) FP64 tile.
+static const size_t kTailScratch = (size_t)80 << 20;
 
 static int gram_splits(int64_t N, int L) {
   const int t = (L + 63) / 64;
@@ -180,6 +183,7 @@ static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
       k ? al(es * (size_t)k) : 0,                                         // Lh
       k ? al(es * (size_t)lzs * k) : 0,                                   // LhP
       k ? al(16 * (size_t)k) : 0,                                         // lz_ab
+      al(kTailScratch),                                                   // SK
   };
   Layout lo{};
   size_t o = 0;
@@ -260,6 +264,8 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
   w.H32 = mixed ? (void *)(b + lo.off[i]) : nullptr; i++;
   w.LV = b + lo.off[i++]; w.LW = b + lo.off[i++]; w.Lh = b + lo.off[i++]; w.LhP = b + lo.off[i++];
   w.lz_ab = (double *)(b + lo.off[i++]);
+  w.SK = b + lo.off[i++];
+  w.sk_bytes = kTailScratch;
   // pinned host mirrors, grown on demand
   if (L > h_cap_L || std::max(lz_steps, 1) > h_cap_lz) {
     CHASE_HIP(hipStreamSynchronize(stream));
@@ -312,6 +318,14 @@ static GemmArgs gargs() {
   return a;
 }
 
+// Arguments of a big-tile GEMM, with the remainder-split scratch attached.
+static GemmArgs bigargs(Ctx &c) {
+  GemmArgs a = gargs();
+  a.tail_ws = c.w.SK;
+  a.tail_ws_bytes = c.w.sk_bytes;
+  return a;
+}
+
 // Alg. 4 with per-vector degrees: one filter-GEMM launch per degree step,
 // each on the active suffix of the degree-sorted block.
 int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, void *bufs[3],
@@ -325,7 +339,7 @@ int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, v
   for (int step = 1; step <= mmax; ++step) {
     const int start =
         (int)(std::lower_bound(deg_sorted.begin(), deg_sorted.end(), step) - deg_sorted.begin());
-    GemmArgs a = gargs();
+    GemmArgs a = bigargs(c);
     a.A = H; a.lda = ldh;
     a.B = bufs[(step - 1) % 3]; a.ldb = ldb;
     a.M = (int)N; a.N = ncols - start; a.K = (int)N;
@@ -427,7 +441,7 @@ static void potrf(Ctx &c, bool cplx, int L, int pass, int inject) {
 
 // Xout = Xin R^{-1} (R^{-1} upper triangular: K range capped per column block).
 static void trsm(Ctx &c, bool cplx, const void *Xin, void *Xout, int64_t ld, int64_t N, int L) {
-  GemmArgs a = gargs();
+  GemmArgs a = bigargs(c);
   a.A = Xin; a.lda = ld;
   a.B = c.w.Ri; a.ldb = L;
   a.M = (int)N; a.N = L; a.K = L;
@@ -505,7 +519,7 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
                    int64_t ldq, int Lp, void *W, void *Vout, int64_t ldv, void *HV, int64_t ldhv) {
   Work &w = c.w;
   {
-    GemmArgs a = gargs();
+    GemmArgs a = bigargs(c);
     a.A = H; a.lda = ldh;
     a.B = Q; a.ldb = ldq;
     a.M = (int)N; a.N = Lp; a.K = (int)N;
@@ -522,7 +536,7 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
                           w.theta, w.E, w.rinfo);
   rocsolver_check(st, cplx ? "rocsolver_zheevd" : "rocsolver_dsyevd");
   {
-    GemmArgs a = gargs();
+    GemmArgs a = bigargs(c);
     a.A = Q; a.lda = ldq;
     a.B = w.A; a.ldb = Lp;
     a.M = (int)N; a.N = Lp; a.K = Lp;
@@ -530,7 +544,7 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
     gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);
   }
   {
-    GemmArgs a = gargs();
+    GemmArgs a = bigargs(c);
     a.A = W; a.lda = N;
     a.B = w.A; a.ldb = Lp;
     a.M = (int)N; a.N = Lp; a.K = Lp;
@@ -557,7 +571,7 @@ void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const voi
   for (int j = 0; j < k; ++j) {
     void *vj = (char *)w.LV + es * (size_t)N * j;
     {
-      GemmArgs a = gargs();
+      GemmArgs a = bigargs(c);
       a.A = H; a.lda = ldh;
       a.B = vj; a.ldb = N;
       a.M = (int)N; a.N = 1; a.K = (int)N;

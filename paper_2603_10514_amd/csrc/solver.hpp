@@ -26,6 +26,8 @@ struct Work {
   void *H32 = nullptr;                                  // N x N in FP32 (mixed)
   void *LV = nullptr, *LW = nullptr, *Lh = nullptr, *LhP = nullptr;  // Lanczos
   double *lz_ab = nullptr;
+  void *SK = nullptr;                                   // remainder-split partials
+  size_t sk_bytes = 0;
   // pinned host mirrors
   double *h_theta = nullptr, *h_resid = nullptr, *h_ab = nullptr;
   int *h_flag = nullptr, *h_ints = nullptr;
