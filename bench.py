@@ -17,7 +17,13 @@ roofline: the filter kernel's algorithmic flops / its device time (HIP
 events recorded by the library around every filter phase on its stream).
 cpu_baseline: the CPU oracle's filter on a bounded sample of the same matrix.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
+
+c3 also solves the same matrix in plain FP64 and reports both
+times-to-solution at the same tolerance.  c5 is the serving stream (Poisson
+arrivals of 5-step correlated sequences, N log-uniform in [2000, 25000], FP32
+filter): it prints p50/p99 latency and throughput, once at the specified
+arrival rate and once at 70% of the capacity measured in the first run.
 """
 import argparse
 import json
@@ -43,6 +49,7 @@ WORKLOADS = {
     "c3": dict(name="complex Hermitian N=30000 DFT-like spectrum, nev=1500 nex=400, FP32 filter / FP64 rest",
                N=30000, cplx=True, family="dft", nev=1500, nex=400, degree=20, min_deg=10,
                max_deg=36, tol=1e-10, precision=1, seed=3),
+    "c5": dict(name="serving stream"),
     "c4": dict(name="real symmetric N=10000 ill-conditioning stress spectrum, nev=200 nex=100, degrees up to 60",
                N=10000, cplx=False, family="stress", nev=200, nex=100, degree=20, min_deg=1,
                max_deg=60, tol=1e-10, precision=0, seed=4),
@@ -84,6 +91,65 @@ def cpu_baseline(H_dev, wl, cols, degree):
                                                                           flops / 1e12, dt))
 
 
+def serving(args):
+    import torch
+    from paper_2603_10514_amd import serve
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    reqs = serve.make_stream(args.requests, args.rate, 2000, 25000, 5, dev, progress=log)
+    torch.cuda.synchronize()
+    log("generated %d request inputs in %.1f s" % (len(reqs), time.perf_counter() - t0))
+    srv = serve.Server(n_slots=args.slots, N_max=25000, device=dev)
+
+    def summary(done, wall):
+        st = serve.latency_stats(done)
+        flops = sum(8.0 * r.N ** 2 * sum(i["matvecs"] for i in r.infos) for r in done)
+        ok = all(all(x == 0 for x in r.status) for r in done)
+        err = max(float(np.max(np.abs(r.evals[0] - r.lam[:r.nev]))) / float(np.max(np.abs(r.lam)))
+                  for r in done)
+        maxres = max(float(np.max(x)) for r in done for x in r.resid)
+        return dict(p50_s=st["p50"], p99_s=st["p99"], mean_s=st["mean"], makespan_s=wall,
+                    throughput_req_s=len(done) / wall, filter_tflops_aggregate=flops / wall / 1e12,
+                    all_converged=ok, max_eig_err_rel_step0=err, max_resid=maxres,
+                    requests=len(done))
+
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    spec = summary(done, wall)
+    log("as specified (%.1f/s): %s" % (args.rate, spec))
+    cap = spec["throughput_req_s"]
+    rate2 = 0.7 * cap
+    sub = reqs[: max(2, args.requests // 2)]
+    rng = np.random.default_rng(6)
+    t = 0.0
+    fresh = []
+    for r in sub:
+        t += rng.exponential(1.0 / rate2)
+        fresh.append(serve.Request(rid=r.rid, arrival=t, N=r.N, nev=r.nev, nex=r.nex, H0=r.H0,
+                                   lam=r.lam, steps=r.steps, eps=r.eps, seed=r.seed))
+    t0 = time.perf_counter()
+    done2 = srv.run(fresh)
+    wall2 = time.perf_counter() - t0
+    sus = summary(done2, wall2)
+    log("sustainable (%.3f/s): %s" % (rate2, sus))
+    srv.close()
+    out = {
+        "metric": "ChASE serving p50/p99 latency (continuous batching, warm-started sequences)",
+        "value": spec["p99_s"], "unit": "s", "n_gpus": 1, "steps": len(done), "warmup": 0,
+        "ms_per_step": spec["makespan_s"] / len(done) * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "complex64 filter / complex128 rest",
+        "data": "synthetic",
+        "config": {"workload": "Poisson arrivals of 5-step correlated complex Hermitian sequences "
+                               "H_{j+1} = H_j + 1e-3 E, N log-uniform in [2000, 25000], nev = 5% N, "
+                               "nex = max(20, 1.5% N), FP32 filter, HBM admission",
+                   "rate_per_s": args.rate, "requests": args.requests, "slots": args.slots},
+        "as_specified": spec,
+        "sustainable": dict(sus, rate_per_s=rate2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,11 +159,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=192)
     ap.add_argument("--cpu-degree", type=int, default=20)
+    ap.add_argument("--requests", type=int, default=12)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--no-fp64-compare", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c5":
+        serving(args)
+        return
 
     import torch
     import paper_2603_10514_amd as P
@@ -181,6 +255,22 @@ def main():
                      "launches": launches, "avg_launch_ms": t_filter / max(launches, 1) * 1e3,
                      "flops_per_launch": flops / max(launches, 1)},
     }
+    if wl["precision"] == 1:
+        mv32 = sum(r["info"]["matvecs_fp32"] for r in results)
+        t32 = sum(r["info"]["t_filter_fp32"] for r in results)
+        out["mixed"] = {"fp32_filter_tflops": f * float(N) ** 2 * mv32 / max(t32, 1e-12) / 1e12,
+                        "fp32_frac_of_peak": f * float(N) ** 2 * mv32 / max(t32, 1e-12) / 1e12 / PEAK["f32"],
+                        "fp32_matvec_share": mv32 / max(matvecs, 1),
+                        "fp32_iters_per_solve": fp32_iters / args.steps}
+        if not args.no_fp64_compare:
+            r64 = P.chase_solve(H, nev, nex, wl["degree"], wl["tol"], evecs=evecs, seed=1000,
+                                min_deg=wl["min_deg"], max_deg=wl["max_deg"], precision=0)
+            out["mixed"]["fp64_time_to_solution_s"] = r64["info"]["t_total"]
+            out["mixed"]["fp64_max_eig_err_rel"] = float(np.max(np.abs(r64["evals"] - lam[:nev]))) / scale
+            out["mixed"]["mixed_vs_fp64_speedup"] = r64["info"]["t_total"] / (wall / args.steps)
+            out["mixed"]["max_abs_eig_diff_mixed_vs_fp64_rel"] = float(
+                np.max(np.abs(results[0]["evals"] - r64["evals"]))) / scale
+            log("fp64 comparison: %.2f s" % r64["info"]["t_total"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(H, wl, args.cpu_cols, args.cpu_degree)
     print(json.dumps(out), flush=True)

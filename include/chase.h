@@ -127,6 +127,8 @@ typedef struct chase_info {
   double lambda_1, lambda_l, lambda_max; /* bounds used by the first filter     */
   int64_t matvecs_fp32;      /* part of matvecs filtered in FP32                */
   double t_filter_fp32;      /* part of t_filter spent in FP32 filter steps     */
+  double ritz_max;           /* largest Ritz value of the last Rayleigh-Ritz
+                                (the lambda_l estimate for a warm restart)      */
 } chase_info;
 
 /* Defaults: dtype REAL64, FP64, deg_opt 1, degrees [1, 36], margin 2,

@@ -71,7 +71,8 @@ class ChaseInfo(ctypes.Structure):
                 ("t_rr", ctypes.c_double), ("t_resid", ctypes.c_double),
                 ("t_lanczos", ctypes.c_double), ("lambda_1", ctypes.c_double),
                 ("lambda_l", ctypes.c_double), ("lambda_max", ctypes.c_double),
-                ("matvecs_fp32", ctypes.c_int64), ("t_filter_fp32", ctypes.c_double)]
+                ("matvecs_fp32", ctypes.c_int64), ("t_filter_fp32", ctypes.c_double),
+                ("ritz_max", ctypes.c_double)]
 
 
 _p = ctypes.c_void_p

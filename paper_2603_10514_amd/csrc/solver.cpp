@@ -742,6 +742,7 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     rec.c = cc; rec.e = e; rec.gamma = gamma; rec.lam1 = lam1;
     if (o.log_cb) o.log_cb(&rec, o.log_user);
     k = j;
+    inf.ritz_max = th.back();
     theta_act.assign(th.begin() + newly, th.end());
     r_act.assign(rr.begin() + newly, rr.end());
     if (k >= nev) break;

@@ -1,0 +1,266 @@
+"""Continuous-batching serving loop over asynchronous solver handles.
+
+A request is a correlated sequence of Hermitian eigenproblems
+H_{j+1} = H_j + eps * E_j (E_j Hermitian Gaussian, E|g|^2 = 1, scaled by
+1/(2 sqrt(N))), each solved for the nev lowest pairs and warm-started from the
+previous problem's subspace, which stays in device memory (the warm start of
+Sec. 1.2 of the paper).  The scheduler:
+
+* keeps a FIFO of arrived requests and a fixed set of slots, each owning a
+  library handle (own stream, workspace sized for the largest problem, host
+  worker thread), so solves of different requests overlap on the device;
+* admits the head of the queue into a free slot when the request's device
+  memory (working matrix, perturbation scratch, search block, the part of
+  the workspace the slot does not already hold) fits the HBM budget;
+* keeps an admitted request in its slot for all its steps (continuous
+  batching: a slot frees, the next request enters while the others run);
+* records, per request, arrival-to-completion latency and every step's
+  eigenvalues, residuals and timings.
+
+Only the eigensolver's work runs in the HIP library; torch provides the
+device buffers, the perturbation matrices and the stream for the update.
+"""
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import paper_2603_10514_amd as P
+
+GIB = 1 << 30
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the stream
+    N: int
+    nev: int
+    nex: int
+    H0: object              # column-major device tensor (complex128 or float64)
+    lam: np.ndarray         # planted spectrum of H0 (for checks)
+    steps: int = 5
+    eps: float = 1e-3
+    seed: int = 0
+    # results
+    t_admit: float = None
+    t_done: float = None
+    evals: list = field(default_factory=list)
+    resid: list = field(default_factory=list)
+    infos: list = field(default_factory=list)
+    status: list = field(default_factory=list)
+
+
+def request_shape(N):
+    """nev = 5% of N, nex = max(20, 1.5% of N)."""
+    return max(1, int(round(0.05 * N))), max(20, int(round(0.015 * N)))
+
+
+def data_bytes(N, nev, nex, cplx=True):
+    es = 16 if cplx else 8
+    return es * (3 * N * N + N * (nev + nex))  # H_j, E_j and its Gaussian, block
+
+
+class Slot:
+    """One concurrent execution slot: a library handle and a torch stream."""
+
+    def __init__(self, idx, handle, ws_bytes, stream):
+        self.idx = idx
+        self.handle = handle
+        self.ws_bytes = ws_bytes
+        self.stream = stream
+        self.req = None
+        self.step = 0
+        self.need = 0
+        self.pending = None
+        self.Hk = None
+        self.evecs = None
+        self.bounds = None
+        self.t_step = 0.0
+
+
+class Server:
+    def __init__(self, n_slots=4, N_max=25000, nev_max=None, nex_max=None, precision=P.PREC_MIXED,
+                 hbm_budget=None, reserve=16 * GIB, degree=20, tol=1e-10, min_deg=10, max_deg=36,
+                 device="cuda:0", cplx=True):
+        import torch
+        self.device = torch.device(device)
+        self.cplx = cplx
+        nev_d, nex_d = request_shape(N_max)
+        nev_max = nev_max or nev_d
+        nex_max = nex_max or nex_d
+        self.opts_tmpl = dict(precision=precision, min_deg=min_deg, max_deg=max_deg)
+        o = P.opts_default(**self.opts_tmpl)
+        o.dtype = P.COMPLEX128 if cplx else P.REAL64
+        self.slots = [Slot(i, P.Handle(N_max, nev_max, nex_max, o),
+                           P.chase_workspace_bytes(N_max, nev_max, nex_max, o.dtype, o.precision),
+                           torch.cuda.Stream(device=self.device)) for i in range(n_slots)]
+        free, total = torch.cuda.mem_get_info(self.device)
+        # the slots' workspaces are already allocated: the budget covers
+        # request data on top of them
+        self.budget = hbm_budget if hbm_budget is not None else max(0, free - reserve)
+        self.used = 0
+        self.peak_used = 0
+        self.degree, self.tol = degree, tol
+        self.N_max, self.nev_max, self.nex_max = N_max, nev_max, nex_max
+        self.log = []
+
+    # ------------------------------------------------------------------ API
+    def run(self, requests, clock=None):
+        """Serve requests (sorted by arrival) until all have finished.
+        Returns the list of requests with their results filled in."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        for r in reqs:
+            if r.N > self.N_max or r.nev > self.nev_max or r.nex > self.nex_max:
+                raise ValueError("request %d larger than the server's maximum shape" % r.rid)
+            if data_bytes(r.N, r.nev, r.nex, self.cplx) > self.budget:
+                raise ValueError("request %d can never fit the HBM budget" % r.rid)
+        import torch
+        torch.cuda.synchronize(self.device)  # inputs generated on other streams
+        t0 = time.perf_counter() if clock is None else clock
+        waiting = []
+        nxt = 0
+        done = 0
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                waiting.append(reqs[nxt])
+                nxt += 1
+            progressed = False
+            # completions
+            for s in self.slots:
+                if s.pending is None:
+                    continue
+                st = s.handle.query()
+                if st == P.CHASE_EBUSY:
+                    continue
+                self._finish_step(s, st, time.perf_counter() - t0)
+                progressed = True
+                if s.req is None:
+                    done += 1
+            # admission (FIFO, head of line)
+            for s in self.slots:
+                if s.req is not None or not waiting:
+                    continue
+                r = waiting[0]
+                need = data_bytes(r.N, r.nev, r.nex, self.cplx)
+                if self.used + need > self.budget:
+                    break
+                waiting.pop(0)
+                self._admit(s, r, need, time.perf_counter() - t0)
+                progressed = True
+            if not progressed:
+                if nxt < len(reqs) and not waiting and all(s.req is None for s in self.slots):
+                    time.sleep(max(0.0, min(0.01, reqs[nxt].arrival - now)))
+                else:
+                    time.sleep(0.0005)
+        return reqs
+
+    def close(self):
+        for s in self.slots:
+            s.handle.close()
+
+    # ------------------------------------------------------------- internals
+    def _admit(self, s, r, need, now):
+        import torch
+        r.t_admit = now
+        s.req = r
+        s.step = 0
+        s.need = need
+        self.used += need
+        self.peak_used = max(self.peak_used, self.used)
+        with torch.cuda.stream(s.stream):
+            s.Hk = torch.empty_strided(r.H0.shape, r.H0.stride(), dtype=r.H0.dtype,
+                                       device=self.device)
+            s.Hk.copy_(r.H0)
+            s.evecs = P.colmajor_empty(r.N, r.nev + r.nex, r.H0.dtype, self.device)
+        s.bounds = None
+        self._launch(s)
+
+    def _perturb(self, s):
+        """H_{j+1} = H_j + eps * E_j on the slot's torch stream."""
+        import torch
+        r = s.req
+        with torch.cuda.stream(s.stream):
+            E = perturbation(r.N, r.seed, s.step, r.eps, r.H0.dtype, self.device)
+            s.Hk.add_(E)
+            del E
+
+    def _launch(self, s):
+        import torch
+        r = s.req
+        if s.step > 0:
+            self._perturb(s)
+        s.stream.synchronize()  # the handle's stream starts after the update
+        o = P.opts_default(**self.opts_tmpl)
+        o.seed = r.seed * 7919 + 1
+        if s.step > 0:
+            # warm start: previous subspace and bounds; eigenvalues move by at
+            # most ||eps E||_2 (Weyl), so the upper bound is widened by that
+            lo, mid, hi = s.bounds
+            shift = 4.0 * r.eps * math.sqrt(2.0)
+            o.warm_start = 1
+            o.have_bounds = 1
+            o.lambda_1, o.lambda_l, o.lambda_max = lo - shift, mid, hi + shift
+        s.pending = s.handle.solve_async(s.Hk, r.nev, r.nex, self.degree, self.tol, s.evecs, o)
+        s.t_step = time.perf_counter()
+
+    def _finish_step(self, s, status, now):
+        r = s.req
+        evals, resid, info = s.pending
+        s.pending = None
+        inf = P._info_dict(info)
+        inf["wall"] = time.perf_counter() - s.t_step
+        r.evals.append(evals.copy())
+        r.resid.append(resid.copy())
+        r.infos.append(inf)
+        r.status.append(status)
+        # bounds for the next problem: lowest and largest Ritz values of the
+        # search space and the upper bound of this one
+        s.bounds = (float(evals[0]), float(inf["ritz_max"]), float(inf["lambda_max"]))
+        s.step += 1
+        if s.step < r.steps and status in (P.CHASE_OK, P.CHASE_NOT_CONVERGED):
+            self._launch(s)
+            return
+        r.t_done = now
+        s.req = None
+        s.Hk = None
+        s.evecs = None
+        self.used -= s.need
+
+
+def make_stream(n_requests, rate, N_lo, N_hi, seed, device, cplx=True, steps=5, eps=1e-3,
+                progress=None):
+    """Poisson arrivals at `rate` per second with N log-uniform in
+    [N_lo, N_hi]; the first matrix of each request is generated up front in
+    device memory (DFT-like planted spectrum, scaled to N)."""
+    import synth
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        N = int(round(math.exp(rng.uniform(math.log(N_lo), math.log(N_hi)))))
+        nev, nex = request_shape(N)
+        H0, lam = synth.planted_torch(N, "dft", 10_000 + i, cplx, device)
+        out.append(Request(rid=i, arrival=t, N=N, nev=nev, nex=nex, H0=H0, lam=lam, steps=steps,
+                           eps=eps, seed=100 + i))
+        if progress:
+            progress("generated request %d: N=%d nev=%d nex=%d" % (i, N, nev, nex))
+    return out
+
+
+def perturbation(N, seed, step, eps, dtype, device):
+    """The E_j that the server adds at `step` (for checks outside it)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1000 + step)
+    G = torch.randn((N, N), dtype=dtype, device=device, generator=g)
+    return (G + G.conj().T) * (eps / (2.0 * math.sqrt(N)))
+
+
+def latency_stats(reqs):
+    lat = np.array([r.t_done - r.arrival for r in reqs])
+    return dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                mean=float(lat.mean()), max=float(lat.max()))
