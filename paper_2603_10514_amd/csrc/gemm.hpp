@@ -141,14 +141,17 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &p, int i, int j, 
   }
 }
 
+// M3 (complex only): three real products per complex one,
+// P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2,
+// im = P3 - P1 - P2 (a quarter fewer MFMAs than the four-product form).
 template <typename T, bool CPLX, bool AT, bool CONJA, int BM, int BN, int BK, int WM, int WN,
-          int EPI, typename FT, int MINB>
-__global__ __launch_bounds__(256, MINB) void gemm_kernel(const GemmArgs p) {
+          int EPI, typename FT, int MINB, bool M3>
+__global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(const GemmArgs p) {
   typedef typename MemT<T, CPLX>::type E;
   typedef typename Mfma<T>::acc Acc;
-  constexpr int NT = 256;
   constexpr int NWM = BM / WM;
-  static_assert(NWM * (BN / WN) == 4, "four waves per block");
+  constexpr int NT = 64 * NWM * (BN / WN);
+  static_assert(!M3 || CPLX, "three-product form is for complex data");
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int NP = CPLX ? 2 : 1;
   constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
@@ -187,14 +190,19 @@ __global__ __launch_bounds__(256, MINB) void gemm_kernel(const GemmArgs p) {
   const GE *Ag = (const GE *)p.A;
   const GE *Bg = (const GE *)p.B;
 
-  Acc accR[FM][FN];
-  Acc accI[FM][FN];
+  Acc accR[FM][FN];  // M3: P1
+  Acc accI[FM][FN];  // M3: P2
+  Acc acc3[M3 ? FM : 1][M3 ? FN : 1];  // M3: P3
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
     for (int b = 0; b < FN; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+      for (int r = 0; r < 4; ++r) {
+        accR[a][b][r] = 0;
+        accI[a][b][r] = 0;
+        if constexpr (M3) acc3[a][b][r] = 0;
+      }
 
   E ra[AE], rb[BE];
   const E zero = mmake<E, T>((T)0, (T)0);
@@ -263,15 +271,31 @@ __global__ __launch_bounds__(256, MINB) void gemm_kernel(const GemmArgs p) {
         br[b] = Bs[buf][0][kk + lk][wn * WN + b * 16 + lr];
         if constexpr (CPLX) bi[b] = Bs[buf][NP - 1][kk + lk][wn * WN + b * 16 + lr];
       }
+      if constexpr (M3) {
+        T as_[FM], bs_[FN];
 #pragma unroll
-      for (int a = 0; a < FM; ++a) {
+        for (int a = 0; a < FM; ++a) as_[a] = ar[a] + ai[a];
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          accR[a][b] = Mfma<T>::op(ar[a], br[b], accR[a][b]);
-          if constexpr (CPLX) {
-            accR[a][b] = Mfma<T>::op(-ai[a], bi[b], accR[a][b]);
-            accI[a][b] = Mfma<T>::op(ar[a], bi[b], accI[a][b]);
-            accI[a][b] = Mfma<T>::op(ai[a], br[b], accI[a][b]);
+        for (int b = 0; b < FN; ++b) bs_[b] = br[b] + bi[b];
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            accR[a][b] = Mfma<T>::op(ar[a], br[b], accR[a][b]);
+            accI[a][b] = Mfma<T>::op(ai[a], bi[b], accI[a][b]);
+            acc3[a][b] = Mfma<T>::op(as_[a], bs_[b], acc3[a][b]);
+          }
+      } else {
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            accR[a][b] = Mfma<T>::op(ar[a], br[b], accR[a][b]);
+            if constexpr (CPLX) {
+              accR[a][b] = Mfma<T>::op(-ai[a], bi[b], accR[a][b]);
+              accI[a][b] = Mfma<T>::op(ar[a], bi[b], accI[a][b]);
+              accI[a][b] = Mfma<T>::op(ai[a], br[b], accI[a][b]);
+            }
           }
         }
       }
@@ -282,6 +306,18 @@ __global__ __launch_bounds__(256, MINB) void gemm_kernel(const GemmArgs p) {
   }
 
   // ---------------------------------------------------------- epilogue --
+  if constexpr (M3) {  // (P1, P2, P3) -> (re, im)
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T p1 = accR[a][b][r], p2 = accI[a][b][r];
+          accR[a][b][r] = p1 - p2;
+          accI[a][b][r] = acc3[a][b][r] - p1 - p2;
+        }
+  }
   if (p.Pk != nullptr) {  // raw partial tile of one K split
     typedef E __attribute__((address_space(1))) GEw;
     GEw *Pt = (GEw *)p.Pk + ((int64_t)(logical - p.tile0) * gridDim.y + blockIdx.y) * (BM * BN);

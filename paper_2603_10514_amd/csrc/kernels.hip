@@ -390,15 +390,25 @@ void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int nelem
 #ifndef CHASE_BIG_BK_REAL
 #define CHASE_BIG_BK_REAL 16
 #endif
+// Complex big tiles: three-product form (M3) on waves of 32 x 32.  Measured
+// at N = 20000 x 1300 columns (filter, algorithmic 8 flops per complex MAC):
+// FP64 four-product 128x64 62.8 TFLOP/s, M3 128x64 (8 waves) 73.1, M3 64x64
+// (4 waves, 3 blocks / CU) 78.5; FP32 122.3 / 146.6 / 145.2.
+#ifndef CHASE_CPLX_3M
+#define CHASE_CPLX_3M 1
+#endif
+#ifndef CHASE_CPLX_3M_BM
+#define CHASE_CPLX_3M_BM 64
+#endif
 constexpr int kBK = 16;
 int gemm_bk() { return kBK; }
 
 // Blocks of one launch that run at once (occupancy x compute units).
-template <typename K> static int resident_blocks(K kernel) {
+template <typename K> static int resident_blocks(K kernel, int nthreads) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess) {
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nthreads, 0) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
@@ -407,13 +417,15 @@ template <typename K> static int resident_blocks(K kernel) {
 
 template <typename T, bool CPLX, bool AT, int EPI, typename FT, int SHAPE>
 static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
-  constexpr int BM = SHAPE == GEMM_BIG ? 128 : 64;
+  constexpr bool M3 = CPLX && SHAPE == GEMM_BIG && CHASE_CPLX_3M;
+  constexpr int BM = SHAPE == GEMM_BIG ? (M3 ? CHASE_CPLX_3M_BM : 128) : 64;
   constexpr int BN = SHAPE == GEMM_BIG ? (CPLX ? 64 : 128) : 64;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int WM = M3 ? 32 : BM / 2, WN = M3 ? 32 : BN / 2;
+  constexpr int NT = 64 * (BM / WM) * (BN / WN);
   constexpr int BK = SHAPE == GEMM_BIG ? (CPLX ? CHASE_BIG_BK_CPLX : CHASE_BIG_BK_REAL) : kBK;
   constexpr int MINB = 1;
   static_assert(kBK % BK == 0, "split granularity");
-  auto kernel = gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BK, WM, WN, EPI, FT, MINB>;
+  auto kernel = gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BK, WM, WN, EPI, FT, MINB, M3>;
   const int nbm = (a.M + BM - 1) / BM, nbn = (a.N + BN - 1) / BN;
   if (nbm <= 0 || nbn <= 0) return;
   if (splits < 1) splits = 1;
@@ -426,7 +438,7 @@ static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   // are split along K across the idle slots of that wave; their partial sums
   // go to the scratch and a reduce kernel applies the epilogue.
   if (SHAPE == GEMM_BIG && splits == 1 && !a.tri && a.tail_ws != nullptr) {
-    static const int C = resident_blocks(kernel);
+    static const int C = resident_blocks(kernel, NT);
     const size_t es = sizeof(T) * (CPLX ? 2 : 1);
     const int full = C > 0 ? (T_ / C) * C : T_;
     const int R = T_ - full;
@@ -436,14 +448,14 @@ static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
       if (full > 0) {
         GemmArgs b = a;
         b.ntiles = full;
-        hipLaunchKernelGGL(kernel, dim3((unsigned)full, 1), dim3(256), 0, s, b);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)full, 1), dim3(NT), 0, s, b);
       }
       GemmArgs b = a;
       b.tile0 = full;
       b.ntiles = R;
       b.Pk = a.tail_ws;
       b.k_per_split = ((a.K + S - 1) / S + kBK - 1) / kBK * kBK;
-      hipLaunchKernelGGL(kernel, dim3((unsigned)R, (unsigned)S), dim3(256), 0, s, b);
+      hipLaunchKernelGGL(kernel, dim3((unsigned)R, (unsigned)S), dim3(NT), 0, s, b);
       const int64_t elems = (int64_t)R * BM * BN;
       hipLaunchKernelGGL((gemm_reduce_kernel<T, CPLX, BM, BN, EPI, FT>),
                          dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, b, S);
@@ -451,7 +463,7 @@ static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
     }
   }
   dim3 grid((unsigned)T_, (unsigned)splits);
-  hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(kernel, grid, dim3(NT), 0, s, a);
 }
 
 void gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,
