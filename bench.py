@@ -60,6 +60,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_sha():
+    """Hash of the GEMM kernel source and its tuning constants."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2603_10514_amd", "csrc")
+    src = open(os.path.join(csrc, "gemm.hpp")).read()
+    src += "".join(l for l in open(os.path.join(csrc, "kernels.hip")) if l.startswith("#define CHASE_"))
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """Calibrated FETCH_SIZE + WRITE_SIZE bytes per filter dispatch from the
+    committed rocprofv3 summary, or None when the kernel changed since."""
+    if workload != "c2":
+        return None
+    f = os.path.join(ROOT, "profiles", "filter_gemm_c2_complex_n20000_pmc.md")
+    if not os.path.exists(f):
+        return None
+    vals = {}
+    for line in open(f):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_dispatch", "kernel_source_sha"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return float(vals["traffic_bytes_per_dispatch"])
+
+
 def cpu_baseline(H_dev, wl, cols, degree):
     """The oracle's filter (numpy, all host cores) on `cols` columns of the
     same matrix at a fixed degree: a bounded sample of the dominant phase."""
@@ -163,6 +190,9 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--cache-dir", default=None,
+                    help="save the generated matrix here, or load it if already saved")
+    ap.add_argument("--generate-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -182,10 +212,26 @@ def main():
     N, nev, nex = wl["N"], wl["nev"], wl["nex"]
     L = nev + nex
     t0 = time.perf_counter()
-    H, lam = synth.planted_torch(N, wl["family"], wl["seed"], wl["cplx"], dev)
-    torch.cuda.synchronize()
-    log("generated H (N=%d, %s) in %.1f s" % (N, "complex" if wl["cplx"] else "real",
-                                                time.perf_counter() - t0))
+    cache = os.path.join(args.cache_dir, "H_%s.npy" % args.workload) if args.cache_dir else None
+    if cache and os.path.exists(cache) and os.path.exists(cache + ".lam.npy"):
+        # the same seeded matrix, generated by an earlier run of this script
+        Hn = np.load(cache, mmap_mode="r")  # row-major H^T == column-major H
+        H = torch.from_numpy(np.ascontiguousarray(Hn)).to(dev).T
+        lam = np.load(cache + ".lam.npy")
+        del Hn
+        log("loaded H (N=%d) from %s in %.1f s" % (N, cache, time.perf_counter() - t0))
+    else:
+        H, lam = synth.planted_torch(N, wl["family"], wl["seed"], wl["cplx"], dev)
+        torch.cuda.synchronize()
+        log("generated H (N=%d, %s) in %.1f s" % (N, "complex" if wl["cplx"] else "real",
+                                                    time.perf_counter() - t0))
+        if cache:
+            os.makedirs(args.cache_dir, exist_ok=True)
+            np.save(cache, H.T.contiguous().cpu().numpy())
+            np.save(cache + ".lam.npy", lam)
+            log("saved H to %s" % cache)
+    if args.generate_only:
+        return
     dt = torch.complex128 if wl["cplx"] else torch.float64
     evecs = P.colmajor_empty(N, L, dt, dev)
     opts = dict(min_deg=wl["min_deg"], max_deg=wl["max_deg"], precision=wl["precision"])
@@ -214,6 +260,7 @@ def main():
     launches = sum(r["info"]["filter_launches"] for r in results)
     fp32_iters = sum(r["info"]["filter_fp32_iters"] for r in results)
     iters = sum(r["info"]["iters"] for r in results)
+    n_steps = sum(x["deg_max"] for r in results for x in r["log"])  # degree steps
     # per-precision filter rates; the roofline entry is the kernel with the
     # larger share of filter time (FP32 and FP64 flops are never mixed)
     mv32 = sum(r["info"]["matvecs_fp32"] for r in results)
@@ -258,7 +305,13 @@ def main():
         "max_resid": max_res,
         "converged": status_ok,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[prec], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[prec],
+                     "traffic": measured_traffic(args.workload),
+                     "traffic_unit": "bytes per filter dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     # es (N^2 + 3 N l') per degree step (H once; X, X_prev and the
+                     # output once), summed over the steps, per dispatch
+                     "algorithmic_bytes_per_dispatch": (16.0 if wl["cplx"] else 8.0) * (
+                         float(N) ** 2 * n_steps + 3.0 * N * matvecs) / max(launches, 1),
                      "kernel": "filter GEMM (gemm_kernel, EPI_FILTER, %s)" % prec,
                      # complex products run as three real MFMA products, so
                      # the MFMA units execute 3/4 of the algorithmic flops

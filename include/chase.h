@@ -121,7 +121,9 @@ typedef struct chase_info {
   int32_t iters;
   int32_t converged;         /* locked pairs (== nev on success)               */
   int64_t matvecs;           /* sum of all degrees over all iterations         */
-  int32_t filter_launches;   /* filter-kernel launches (one per degree step)   */
+  int32_t filter_launches;   /* filter GEMM kernel dispatches (one per degree
+                                step, two when the step's last partial wave is
+                                split along K)                                 */
   int32_t filter_fp32_iters; /* iterations whose filter ran in FP32            */
   double t_total, t_filter, t_qr, t_rr, t_resid, t_lanczos; /* seconds          */
   double lambda_1, lambda_l, lambda_max; /* bounds used by the first filter     */

@@ -416,7 +416,7 @@ template <typename K> static int resident_blocks(K kernel, int nthreads) {
 }
 
 template <typename T, bool CPLX, bool AT, int EPI, typename FT, int SHAPE>
-static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
+static int gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   constexpr bool M3 = CPLX && SHAPE == GEMM_BIG && CHASE_CPLX_3M;
   constexpr int BM = SHAPE == GEMM_BIG ? (M3 ? CHASE_CPLX_3M_BM : 128) : 64;
   constexpr int BN = SHAPE == GEMM_BIG ? (CPLX ? 64 : 128) : 64;
@@ -427,7 +427,7 @@ static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   static_assert(kBK % BK == 0, "split granularity");
   auto kernel = gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BK, WM, WN, EPI, FT, MINB, M3>;
   const int nbm = (a.M + BM - 1) / BM, nbn = (a.N + BN - 1) / BN;
-  if (nbm <= 0 || nbn <= 0) return;
+  if (nbm <= 0 || nbn <= 0) return 0;
   if (splits < 1) splits = 1;
   if (a.k_per_split <= 0) a.k_per_split = ((a.K + kBK - 1) / kBK) * kBK;
   const int T_ = nbm * nbn;
@@ -459,32 +459,29 @@ static void gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
       const int64_t elems = (int64_t)R * BM * BN;
       hipLaunchKernelGGL((gemm_reduce_kernel<T, CPLX, BM, BN, EPI, FT>),
                          dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, b, S);
-      return;
+      return full > 0 ? 2 : 1;
     }
   }
   dim3 grid((unsigned)T_, (unsigned)splits);
   hipLaunchKernelGGL(kernel, grid, dim3(NT), 0, s, a);
+  return 1;
 }
 
-void gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,
-          GemmArgs &a, int splits, hipStream_t s) {
+int gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,
+         GemmArgs &a, int splits, hipStream_t s) {
   if (epi_filter) {  // filter steps: A = H read K-contiguous, big tiles
     if (prec32) {
       if (!out64) throw InvalidArg();
-      if (cplx) gemm_launch<float, true, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
-      else gemm_launch<float, false, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
-    } else {
-      if (cplx) gemm_launch<double, true, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
-      else gemm_launch<double, false, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
+      if (cplx) return gemm_launch<float, true, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
+      return gemm_launch<float, false, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
     }
-    return;
+    if (cplx) return gemm_launch<double, true, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
+    return gemm_launch<double, false, true, EPI_FILTER, double, GEMM_BIG>(a, splits, s);
   }
   if (prec32) throw InvalidArg();
 #define G_CASE(C, A, S)                                                                  \
-  if (cplx == C && at == A && shape == S) {                                              \
-    gemm_launch<double, C, A, EPI_AXPBY, double, S>(a, splits, s);                       \
-    return;                                                                              \
-  }
+  if (cplx == C && at == A && shape == S)                                                \
+    return gemm_launch<double, C, A, EPI_AXPBY, double, S>(a, splits, s);
   G_CASE(false, false, GEMM_BIG)
   G_CASE(false, true, GEMM_BIG)
   G_CASE(false, false, GEMM_SMALL)

@@ -13,8 +13,10 @@ struct GemmArgs;
 // dtype-erased GEMM dispatch.  prec32: operands are float / float2.
 // at: A read K-contiguous (conjugated when complex); otherwise M-contiguous.
 // epi_filter: EPI_FILTER epilogue (final outputs in FP64 when out64 is set).
-void gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,
-          GemmArgs &args, int splits, hipStream_t s);
+// Returns the number of GEMM kernel dispatches (the remainder split adds
+// one; its reduce kernel is not counted).
+int gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,
+         GemmArgs &args, int splits, hipStream_t s);
 int gemm_bk();  // K chunk of the GEMM tiles (the split granularity)
 
 // G (n x n) = sum over nsplit partials S, mirrored to a Hermitian /

@@ -351,8 +351,7 @@ int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, v
     a.Onext = bufs[step % 3]; a.ldn = ldb;
     a.Ofinal = out; a.ldf = ldo;
     a.deg = deg_dev; a.step = step;
-    gemm(cplx, f32, true, true, true, GEMM_BIG, a, 1, c.stream);
-    ++launches;
+    launches += gemm(cplx, f32, true, true, true, GEMM_BIG, a, 1, c.stream);
     sprev = s;
     s = 1.0 / (2.0 / sigma1 - s);
   }
