@@ -193,6 +193,10 @@ def main():
     ap.add_argument("--cache-dir", default=None,
                     help="save the generated matrix here, or load it if already saved")
     ap.add_argument("--generate-only", action="store_true")
+    ap.add_argument("--qr-policy", default="auto",
+                    choices=["auto", "chol1", "chol2", "shifted", "householder"],
+                    help="force one QR variant every iteration (Table 3 compares "
+                         "Householder QR with the estimate-driven choice)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -234,7 +238,8 @@ def main():
         return
     dt = torch.complex128 if wl["cplx"] else torch.float64
     evecs = P.colmajor_empty(N, L, dt, dev)
-    opts = dict(min_deg=wl["min_deg"], max_deg=wl["max_deg"], precision=wl["precision"])
+    opts = dict(min_deg=wl["min_deg"], max_deg=wl["max_deg"], precision=wl["precision"],
+                qr_policy=args.qr_policy)
 
     def one(step):
         return P.chase_solve(H, nev, nex, wl["degree"], wl["tol"], evecs=evecs, seed=1000 + step,
@@ -294,7 +299,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "N": N, "nev": nev, "nex": nex,
                    "degree": wl["degree"], "min_deg": wl["min_deg"], "max_deg": wl["max_deg"],
-                   "tol": wl["tol"], "precision": "mixed" if wl["precision"] else "fp64"},
+                   "tol": wl["tol"], "precision": "mixed" if wl["precision"] else "fp64",
+                   "qr_policy": args.qr_policy},
         "time_to_solution_s": wall / args.steps,
         "filter_tflops": flops / t_filter / 1e12,
         "matvecs_per_solve": matvecs / args.steps,

@@ -18,8 +18,8 @@
 //    element of padding so that the transposing stores are conflict-free.
 //  * Block -> tile mapping is XCD aware: consecutive hardware block ids go
 //    round-robin to the 8 XCDs, so each XCD is handed a contiguous range of
-//    logical tiles (N-tile fastest) and the blocks sharing an A row panel run
-//    on the same XCD and reuse it from that XCD's L2.
+//    logical tiles, ordered in bands of tile rows (tile_coords) so that the
+//    blocks resident together share row and column panels in its L2.
 //
 // Epilogues:
 //  EPI_AXPBY   C = alpha * acc + beta * C (beta == 0: C not read); with K
@@ -104,6 +104,22 @@ struct GemmArgs {
   void *tail_ws; size_t tail_ws_bytes;  // scratch the launcher may use for Pk
 };
 
+// Logical tile g -> (tile row, tile column).  Tiles are grouped in bands of
+// GM tile rows walked column by column, so that the blocks resident on one
+// XCD at a time cover about GM rows x (resident / GM) columns and share both
+// their H row panels and their X column panels in that XCD's L2.
+#ifndef CHASE_TILE_GROUP
+#define CHASE_TILE_GROUP 8
+#endif
+__device__ __forceinline__ void tile_coords(int g, int nbm, int nbn, int &bm, int &bn) {
+  constexpr int GM = CHASE_TILE_GROUP;
+  const int band = g / (GM * nbn);
+  const int rows = min(GM, nbm - band * GM);
+  const int r = g - band * GM * nbn;
+  bm = band * GM + r % rows;
+  bn = r / rows;
+}
+
 // The epilogue of one output element (row i, column j of this launch).
 template <typename T, bool CPLX, int EPI, typename FT>
 __device__ __forceinline__ void epilogue_store(const GemmArgs &p, int i, int j, T ar, T ai,
@@ -171,7 +187,8 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
   const int xcd = hb & 7, q = hb >> 3;
   const int per = nb >> 3, rem = nb & 7;
   const int logical = p.tile0 + xcd * per + (xcd < rem ? xcd : rem) + q;
-  const int bm = logical / nbn, bn = logical % nbn;
+  int bm, bn;
+  tile_coords(logical, nbm, nbn, bm, bn);
   const int m0 = bm * BM, n0 = bn * BN;
   if (p.tri && m0 > n0 + BN - 1) return;
 
@@ -361,9 +378,10 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(const GemmArgs p, int 
   const int w = (int)(e % (BM * BN));
   if (tl >= p.ntiles) return;
   const int ii = w % BM, jj = w / BM;
-  const int nbn = (p.N + BN - 1) / BN;
-  const int logical = p.tile0 + tl;
-  const int i = (logical / nbn) * BM + ii, j = (logical % nbn) * BN + jj;
+  const int nbm = (p.M + BM - 1) / BM, nbn = (p.N + BN - 1) / BN;
+  int bm, bn;
+  tile_coords(p.tile0 + tl, nbm, nbn, bm, bn);
+  const int i = bm * BM + ii, j = bn * BN + jj;
   if (i >= p.M || j >= p.N) return;
   const GE *P = (const GE *)p.Pk + (int64_t)tl * S * (BM * BN) + w;
   T sr = 0, si = 0;
