@@ -141,7 +141,8 @@ void chase_opts_default(chase_opts *opts);
 /* ---------------------------------------------------------------- solve --
  * chase_solve: Alg. 1 end to end, synchronous.
  *   H      device, N x N, leading dimension ldh >= N, read only.
- *   nev, nex: 1 <= nev, nev + nex <= N.
+ *   nev, nex: 1 <= nev, 1 <= nex (Alg. 1 needs a search space larger than
+ *          nev), nev + nex <= N.
  *   degree: initial filter degree (Sec. 4.3 uses 20), >= 1.
  *   tol:   residual tolerance of the residual of Sec. 2.3.1 (> 0).
  *   evals  host [nev]: ascending eigenvalues (locked ones first).

@@ -71,8 +71,9 @@ def chase_solve(H, nev, nex, deg=20, tol=1e-10, *, V0, bounds=None,
     H = np.asarray(H)
     N = H.shape[0]
     L = nev + nex
-    if not (1 <= nev and L <= N):
-        raise ValueError("need 1 <= nev and nev + nex <= N")
+    if not (1 <= nev and 1 <= nex and L <= N):
+        # Alg. 1 sets a search space l > nev
+        raise ValueError("need 1 <= nev, 1 <= nex and nev + nex <= N")
     if bounds is None:
         if lanczos_v0 is None:
             raise ValueError("bounds or lanczos_v0 required")

@@ -82,8 +82,9 @@ chase_status check_solve(const void *H, int64_t N, int64_t ldh, int32_t nev, int
   if (H == nullptr || evals == nullptr || evecs == nullptr)
     return fail(CHASE_EINVAL, "H, evals and evecs must not be NULL");
   if (N < 1 || N > 2147483647LL) return fail(CHASE_EINVAL, "need 1 <= N < 2^31");
-  if (nev < 1 || nex < 0 || (int64_t)nev + nex > N)
-    return fail(CHASE_EINVAL, "need 1 <= nev, 0 <= nex, nev + nex <= N");
+  if (nev < 1 || nex < 1 || (int64_t)nev + nex > N)
+    return fail(CHASE_EINVAL,
+                "need 1 <= nev, 1 <= nex (the search space exceeds nev, Alg. 1), nev + nex <= N");
   if (ldh < N || ldv < N) return fail(CHASE_EINVAL, "need ldh >= N and ldv >= N");
   if (degree < 1) return fail(CHASE_EINVAL, "degree must be >= 1");
   if (!(tol > 0.0)) return fail(CHASE_EINVAL, "tol must be > 0");
@@ -141,7 +142,7 @@ chase_status chase_solve(const void *H, int64_t N, int64_t ldh, int32_t nev, int
 
 size_t chase_workspace_bytes(int64_t N, int32_t nev, int32_t nex, chase_dtype dtype,
                              chase_precision precision) {
-  if (N < 1 || nev < 1 || nex < 0 || (int64_t)nev + nex > N) return 0;
+  if (N < 2 || nev < 1 || nex < 1 || (int64_t)nev + nex > N) return 0;
   return work_bytes(N, nev + nex, dtype == CHASE_COMPLEX128, precision == CHASE_PREC_MIXED, 40);
 }
 
@@ -150,7 +151,7 @@ chase_status chase_handle_create(int64_t N_max, int32_t nev_max, int32_t nex_max
   chase_status s = check_opts(opts);
   if (s != CHASE_OK) return s;
   if (out == nullptr) return fail(CHASE_EINVAL, "out is NULL");
-  if (N_max < 1 || nev_max < 1 || nex_max < 0 || (int64_t)nev_max + nex_max > N_max)
+  if (N_max < 2 || nev_max < 1 || nex_max < 1 || (int64_t)nev_max + nex_max > N_max)
     return fail(CHASE_EINVAL, "invalid maximum shape");
   return guarded([&] {
     chase_handle *h = new chase_handle();

@@ -98,7 +98,8 @@ def test_invalid_arguments_rejected_without_gpu(pkg):
                              ev.ctypes.data_as(pkg._dp), ctypes.c_void_p(16), 10, None, None)
     assert st == pkg.CHASE_EINVAL
     o = pkg.opts_default()
-    for bad in [dict(N=10, nev=8, nex=4), dict(N=10, nev=0, nex=2), dict(N=10, nev=2, nex=2, ldh=5),
+    for bad in [dict(N=10, nev=8, nex=4), dict(N=10, nev=0, nex=2), dict(N=10, nev=2, nex=0),
+                dict(N=10, nev=2, nex=2, ldh=5),
                 dict(N=10, nev=2, nex=2, degree=0), dict(N=10, nev=2, nex=2, tol=0.0)]:
         a = dict(N=10, ldh=10, nev=2, nex=2, degree=20, tol=1e-10)
         a.update(bad)

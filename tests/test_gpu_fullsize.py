@@ -67,3 +67,20 @@ def test_solve_full_size(problem, H_host, gpu):
     # the filter (the kernel being timed) dominates, and the history is sane
     assert out["info"]["t_filter"] > 0.5 * out["info"]["t_total"]
     assert 3 <= out["info"]["iters"] <= 12
+
+
+def test_mixed_precision_full_size_n30000(gpu):
+    """The mixed-precision workload at full size: complex N = 30000, nev 1500,
+    nex 400, FP32 filter; eigenvalues against the planted spectrum."""
+    import torch
+    import paper_2603_10514_amd as P
+    H, lam = synth.planted_torch(30000, "dft", 3, True, gpu)
+    out = P.chase_solve(H, 1500, 400, 20, 1e-10, min_deg=10, max_deg=36, seed=1000,
+                        precision=P.PREC_MIXED)
+    torch.cuda.synchronize()
+    assert out["status"] == P.CHASE_OK
+    assert out["info"]["filter_fp32_iters"] >= 1
+    assert np.max(np.abs(out["evals"] - lam[:1500])) <= 1e-10 * np.max(np.abs(lam))
+    assert np.all(out["resid"] < 1e-10)
+    del H
+    torch.cuda.empty_cache()

@@ -189,3 +189,72 @@ def test_fixed_degree_sweep_exercises_alg3(P, gpu, degree):
     assert g["cond_exact"] == pytest.approx(o["cond_exact"], rel=1e-2)
     expect = "chol1" if o["cond_est"] < 20 else ("chol2" if o["cond_est"] <= 1e8 else "shifted")
     assert g["variant"] == expect
+
+
+def _planted_with_multiplicity(N, mult, seed):
+    """Planted spectrum whose lowest eigenvalue has multiplicity `mult`."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    lam = np.sort(rng.uniform(-1, 1, N))
+    lam[:mult] = -1.5
+    H = (Q * lam) @ Q.T
+    return np.asfortranarray(0.5 * (H + H.T)), np.sort(lam)
+
+
+@pytest.mark.parametrize("N,nev,nex", [(2, 1, 1), (5, 2, 3), (40, 3, 1), (130, 10, 120)])
+def test_degenerate_shapes(P, gpu, N, nev, nex):
+    """Tiny orders, a single extra vector, and a search space equal to the
+    whole space (nev + nex = N)."""
+    H, lam = synth.planted_numpy(N, "uniform", 41)
+    V0 = synth.start_block(N, nev + nex, 42)
+    up = lam[-1] + 1e-3 * max(1.0, abs(lam[-1]))
+    lo = lam[min(nev + nex, N) - 1]
+    if lo >= up:
+        lo = lam[0] + 0.5 * (up - lam[0])
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=to_dev(V0, gpu), warm_start=1,
+                        have_bounds=1, lambda_1=lam[0], lambda_l=lo, lambda_max=up)
+    assert out["status"] == P.CHASE_OK
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10 * max(1.0, np.max(np.abs(lam)))
+    assert np.all(out["resid"] < 1e-10)
+
+
+def test_multiple_eigenvalue(P, gpu):
+    """A 6-fold lowest eigenvalue: the eigenvectors are unique only as a
+    subspace, so compare eigenvalues, residuals and the invariant subspace."""
+    N, nev, nex = 400, 12, 8
+    H, lam = _planted_with_multiplicity(N, 6, 43)
+    ref, out = _run(P, gpu, H, lam, nev, nex, False, 44)
+    assert out["status"] == P.CHASE_OK
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10
+    assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10
+    Y = to_host(out["evecs"])[:, :6]
+    Yr = ref.evecs[:, :6]
+    # the two 6-dimensional invariant subspaces coincide
+    s = np.linalg.svd(Yr.T @ Y, compute_uv=False)
+    assert np.min(s) >= 1 - 1e-9
+
+
+def test_exact_warm_start_converges_at_once(P, gpu):
+    N, nev, nex = 300, 10, 6
+    H, lam = synth.planted_numpy(N, "uniform", 45)
+    w, Z = np.linalg.eigh(H)
+    V0 = np.asfortranarray(Z[:, : nev + nex])
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=to_dev(V0, gpu), warm_start=1,
+                        have_bounds=1, lambda_1=lam[0], lambda_l=lam[nev + nex - 1],
+                        lambda_max=lam[-1])
+    assert out["status"] == P.CHASE_OK and out["info"]["iters"] == 1
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-12
+
+
+def test_invalid_arguments_on_device(P, gpu):
+    import torch
+    H = torch.zeros((8, 8), dtype=torch.float64, device=gpu)
+    with pytest.raises(P.ChaseError):
+        P.chase_solve(H, 6, 4)          # nev + nex > N
+    with pytest.raises(P.ChaseError):
+        P.chase_solve(H, 2, 2, degree=0)
+    with pytest.raises(P.ChaseError):
+        P.chase_solve(H, 3, 0)          # Alg. 1 needs nex >= 1
+    with pytest.raises(P.ChaseError):
+        P.chase_filter(H, torch.zeros((8, 2), dtype=torch.float64, device=gpu).T.contiguous().T,
+                       [3, 1], 0.0, 1.0, -2.0)  # degrees not ascending

@@ -88,6 +88,12 @@ def test_householder_vs_dynamic_same_convergence():
     assert np.max(np.abs(auto.evals - hh.evals)) < 1e-12
 
 
+def test_search_space_must_exceed_nev():
+    H, lam = synth.planted_numpy(20, "uniform", 1)
+    with pytest.raises(ValueError):
+        solver.chase_solve(H, 3, 0, V0=synth.start_block(20, 3, 2), bounds=(lam[0], lam[2], lam[-1]))
+
+
 def test_not_converged_reports_partial():
     N, nev, nex = 300, 12, 6
     H, lam = synth.planted_numpy(N, "uniform", 9)
