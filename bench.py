@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--cache-dir", default=None,
                     help="save the generated matrix here, or load it if already saved")
     ap.add_argument("--generate-only", action="store_true")
+    ap.add_argument("--mixed-switch", type=float, default=None,
+                    help="mixed form: switch the filter to FP64 below this residual / ||H||")
     ap.add_argument("--qr-policy", default="auto",
                     choices=["auto", "chol1", "chol2", "shifted", "householder"],
                     help="force one QR variant every iteration (Table 3 compares "
@@ -240,6 +242,8 @@ def main():
     evecs = P.colmajor_empty(N, L, dt, dev)
     opts = dict(min_deg=wl["min_deg"], max_deg=wl["max_deg"], precision=wl["precision"],
                 qr_policy=args.qr_policy)
+    if args.mixed_switch is not None:
+        opts["mixed_switch"] = args.mixed_switch
 
     def one(step):
         return P.chase_solve(H, nev, nex, wl["degree"], wl["tol"], evecs=evecs, seed=1000 + step,

@@ -102,7 +102,8 @@ typedef struct chase_opts {
                                     reports failure (-1 = off)                  */
   double mixed_switch;       /* MIXED: switch the filter to FP64 once the lowest
                                 unconverged residual <= mixed_switch *
-                                max(|lambda_1|, |lambda_max|) (default 6e-5)     */
+                                max(|lambda_1|, |lambda_max|) (default 6e-5), or
+                                once an FP32 iteration fails to halve it         */
   void *stream;              /* hipStream_t or NULL                              */
   void (*log_cb)(const chase_iter_log *rec, void *user);
   void *log_user;

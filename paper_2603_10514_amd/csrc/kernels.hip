@@ -400,6 +400,13 @@ void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int nelem
 #ifndef CHASE_CPLX_3M_BM
 #define CHASE_CPLX_3M_BM 64
 #endif
+// Real big tiles (waves of BM/2 x BN/2).
+#ifndef CHASE_REAL_BM
+#define CHASE_REAL_BM 128
+#endif
+#ifndef CHASE_REAL_BN
+#define CHASE_REAL_BN 128
+#endif
 constexpr int kBK = 16;
 int gemm_bk() { return kBK; }
 
@@ -418,8 +425,8 @@ template <typename K> static int resident_blocks(K kernel, int nthreads) {
 template <typename T, bool CPLX, bool AT, int EPI, typename FT, int SHAPE>
 static int gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   constexpr bool M3 = CPLX && SHAPE == GEMM_BIG && CHASE_CPLX_3M;
-  constexpr int BM = SHAPE == GEMM_BIG ? (M3 ? CHASE_CPLX_3M_BM : 128) : 64;
-  constexpr int BN = SHAPE == GEMM_BIG ? (CPLX ? 64 : 128) : 64;
+  constexpr int BM = SHAPE == GEMM_BIG ? (M3 ? CHASE_CPLX_3M_BM : (CPLX ? 128 : CHASE_REAL_BM)) : 64;
+  constexpr int BN = SHAPE == GEMM_BIG ? (CPLX ? 64 : CHASE_REAL_BN) : 64;
   constexpr int WM = M3 ? 32 : BM / 2, WN = M3 ? 32 : BN / 2;
   constexpr int NT = 64 * (BM / WM) * (BN / WN);
   constexpr int BK = SHAPE == GEMM_BIG ? (CPLX ? CHASE_BIG_BK_CPLX : CHASE_BIG_BK_REAL) : kBK;

@@ -663,6 +663,7 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
   int it = 0;
   const double sw = o.mixed_switch * std::max(std::fabs(gamma), std::fabs(beta));
   bool filter32 = mixed;
+  double rmin_prev = -1.0;
   for (it = 1; it <= o.max_iter; ++it) {
     const double cc = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
     const int Lp = L - k;
@@ -680,8 +681,12 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     for (int a = 0; a < Lp; ++a) w.h_ints[a] = msorted[a];
     CHASE_HIP(hipMemcpyAsync(w.deg, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
     if (mixed && !theta_act.empty()) {
-      double rmin = *std::min_element(r_act.begin(), r_act.end());
-      filter32 = filter32 && rmin > sw;
+      // FP32 while the residuals are above the switch point and still fall:
+      // an FP32 pass that does not halve the lowest unconverged residual has
+      // reached the FP32 floor (about 1e2 u32 ||H||), so FP64 takes over
+      const double rmin = *std::min_element(r_act.begin(), r_act.end());
+      filter32 = filter32 && rmin > sw && !(rmin_prev > 0.0 && rmin > 0.5 * rmin_prev);
+      rmin_prev = rmin;
     }
     const bool f32 = mixed && filter32;
     gather_cols(cplx, f32, evecs, ldv, w.X0, N, (int)N, Lp, w.perm, s);
