@@ -280,6 +280,18 @@ def main():
     else:
         prec, kflops, ktime = "f64", f * float(N) ** 2 * mv64, t64
     achieved = kflops / ktime / 1e12
+    # per-step roofline (Sec. 8(d) of the design): step i with l'_i active
+    # columns cannot take less than max(f N^2 l'_i / peak, s (N^2 + 3 N l'_i) / HBM)
+    es = (16.0 if wl["cplx"] else 8.0) / (2.0 if prec == "f32" else 1.0)
+    t_star = 0.0
+    for r in results:
+        for x in r["log"]:
+            d = np.asarray(x["degrees"])
+            pk = PEAK["f32" if x["filter_prec"] == 1 else "f64"] * 1e12
+            bpe = (16.0 if wl["cplx"] else 8.0) / (2.0 if x["filter_prec"] == 1 else 1.0)
+            for i in range(1, int(d.max()) + 1 if d.size else 1):
+                lp = float(np.sum(d >= i))
+                t_star += max(f * float(N) ** 2 * lp / pk, bpe * (float(N) ** 2 + 3.0 * N * lp) / 8e12)
     scale = float(np.max(np.abs(lam)))
     eig_err = max(float(np.max(np.abs(r["evals"] - lam[:nev]))) / scale for r in results)
     max_res = max(float(np.max(r["resid"])) for r in results)
@@ -307,6 +319,7 @@ def main():
                    "qr_policy": args.qr_policy},
         "time_to_solution_s": wall / args.steps,
         "filter_tflops": flops / t_filter / 1e12,
+        "filter_frac_of_per_step_roofline": t_star / t_filter,
         "matvecs_per_solve": matvecs / args.steps,
         "iters_per_solve": iters / args.steps,
         "phase_s_per_solve": phases,

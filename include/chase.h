@@ -80,6 +80,8 @@ typedef struct chase_iter_log {
   double c, e, gamma, lam1; /* filter centre, half-width, normalisation point,
                                lowest Ritz value (the rho_1 point)              */
   double t_filter, t_qr, t_rr, t_resid; /* seconds, device events               */
+  int32_t ncols;         /* active (filtered) columns of this iteration        */
+  const int32_t *degrees; /* their degrees, ascending (valid during log_cb)    */
 } chase_iter_log;
 
 typedef struct chase_opts {

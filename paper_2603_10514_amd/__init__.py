@@ -39,7 +39,8 @@ class ChaseIterLog(ctypes.Structure):
                 ("e", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("lam1", ctypes.c_double), ("t_filter", ctypes.c_double),
                 ("t_qr", ctypes.c_double), ("t_rr", ctypes.c_double),
-                ("t_resid", ctypes.c_double)]
+                ("t_resid", ctypes.c_double), ("ncols", ctypes.c_int32),
+                ("degrees", ctypes.POINTER(ctypes.c_int32))]
 
 
 LOG_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(ChaseIterLog), ctypes.c_void_p)
@@ -187,8 +188,9 @@ def _info_dict(info):
 
 
 def _log_dict(rec):
-    d = {f: getattr(rec, f) for f, _ in ChaseIterLog._fields_}
+    d = {f: getattr(rec, f) for f, _ in ChaseIterLog._fields_ if f != "degrees"}
     d["variant"] = QR_NAMES.get(d["qr_variant"], "?")
+    d["degrees"] = [rec.degrees[i] for i in range(rec.ncols)] if rec.degrees else []
     return d
 
 

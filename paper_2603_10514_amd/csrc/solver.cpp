@@ -743,6 +743,8 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     rec.chol_failed = q.failed; rec.filter_prec = f32 ? CHASE_PREC_MIXED : CHASE_PREC_FP64;
     rec.deg_min = mmin; rec.deg_max = mmax; rec.matvecs = mv; rec.cond_est = est;
     rec.cond_exact = kappa;
+    rec.ncols = Lp;
+    rec.degrees = msorted.data();
     rec.c = cc; rec.e = e; rec.gamma = gamma; rec.lam1 = lam1;
     if (o.log_cb) o.log_cb(&rec, o.log_user);
     k = j;
