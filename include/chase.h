@@ -190,7 +190,8 @@ void chase_handle_destroy(chase_handle *h);
 
 /* Chebyshev filter with per-vector degrees (Alg. 4, Sec. 2.2): column a of
  * out = p_{m_a}(H) V[:, a], p_m(x) = C_m((x-c)/e) / C_m((gamma-c)/e).
- * degrees: host int32[ncols], ascending, each >= 1.  prec MIXED runs the
+ * degrees: host int32[ncols], ascending, each >= 1 (ncols == 0: no-op, the
+ * pointers are not used).  prec MIXED runs the
  * recurrence in FP32 (H and V rounded to FP32) and writes FP64 results. */
 chase_status chase_filter(chase_dtype dtype, chase_precision prec, const void *H, int64_t N,
                           int64_t ldh, const void *V, int64_t ldv, int32_t ncols,

@@ -227,14 +227,14 @@ chase_status chase_filter(chase_dtype dtype, chase_precision prec, const void *H
                           int64_t ldh, const void *V, int64_t ldv, int32_t ncols,
                           const int32_t *deg, double c, double e, double gamma, void *out,
                           int64_t ldo, void *stream) {
-  if (!H || !V || !out || (!deg && ncols > 0)) return fail(CHASE_EINVAL, "NULL argument");
   if (N < 1 || ncols < 0 || ncols > N || ldh < N || ldv < N || ldo < N)
     return fail(CHASE_EINVAL, "invalid sizes");
+  if (ncols == 0) return CHASE_OK;  // nothing is read or written
+  if (!H || !V || !out || !deg) return fail(CHASE_EINVAL, "NULL argument");
   if (!(e > 0.0)) return fail(CHASE_EINVAL, "half-width e must be > 0");
   for (int a = 0; a < ncols; ++a)
     if (deg[a] < 1 || (a > 0 && deg[a] < deg[a - 1]))
       return fail(CHASE_EINVAL, "degrees must be >= 1 and ascending");
-  if (ncols == 0) return CHASE_OK;
   return guarded([&] {
     const bool cplx = dtype == CHASE_COMPLEX128, f32 = prec == CHASE_PREC_MIXED;
     Ctx &cx = thread_ctx();
