@@ -27,8 +27,11 @@ Parity status per module (the pins live in ``tests/test_oracle_*.py``):
   rr         pinned (full diagonalisation of planted spectra)
   solver     pinned (planted eigenvalues, full diagonalisation, residual bound)
   degrees    parity unpinned (the paper gives no formula; see its docstring)
-  lanczos    parity unpinned beyond the upper-bound property (the paper gives
-             no details of its spectral-bound estimator)
+  lanczos    pinned in part (Gauss-quadrature weights on a matrix with three
+             distinct eigenvalues; top Ritz pair and its residual against a
+             Rayleigh-Ritz on an independently built Krylov basis; the
+             upper-bound property); the choice of the lambda_l estimate is
+             parity unpinned (the paper gives no details of its estimator)
 """
 
 from .chebyshev import cheb_closed, rho_abs, sigma_sequence, scaled_poly_recurrence

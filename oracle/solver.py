@@ -66,7 +66,8 @@ def chase_solve(H, nev, nex, deg=20, tol=1e-10, *, V0, bounds=None,
 
     V0 (N x (nev+nex)) is the start block (random or a warm start); bounds is
     (lambda_1, lambda_l, upper) or None for the Lanczos estimate from
-    lanczos_v0.  qr_policy "auto" is Alg. 3; "chol1", "chol2", "shifted" or
+    lanczos_v0 (one start vector, or an N x nvec block: one run per
+    column).  qr_policy "auto" is Alg. 3; "chol1", "chol2", "shifted" or
     "householder" force one variant every iteration."""
     H = np.asarray(H)
     N = H.shape[0]

@@ -13,9 +13,9 @@ which are not available):
   stress    n_low of lambda ~ U[-1, -0.999], the rest U[-0.5, 1e3]
 """
 from .planted import (spectrum, planted_numpy, start_block, lanczos_start,
-                      perturbation_numpy, planted_torch, start_block_torch,
+                      lanczos_starts, perturbation_numpy, planted_torch, start_block_torch,
                       perturbation_torch)
 
-__all__ = ["spectrum", "planted_numpy", "start_block", "lanczos_start",
+__all__ = ["spectrum", "planted_numpy", "start_block", "lanczos_start", "lanczos_starts",
            "perturbation_numpy", "planted_torch", "start_block_torch",
            "perturbation_torch"]

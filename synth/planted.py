@@ -55,6 +55,12 @@ def lanczos_start(N, seed, cplx=False):
     return _gauss(rng, (N,), cplx)
 
 
+def lanczos_starts(N, nvec, seed, cplx=False):
+    """N x nvec Gaussian start vectors, one per Lanczos run (Fortran order)."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(_gauss(rng, (N, nvec), cplx))
+
+
 def perturbation_numpy(N, seed, cplx=True):
     """E = (G + G^H) / (2 sqrt(N)) with Gaussian G (E|g|^2 = 1)."""
     rng = np.random.default_rng(seed)
