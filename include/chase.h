@@ -98,8 +98,10 @@ typedef struct chase_opts {
   double lambda_1, lambda_l, lambda_max; /* lambda_max must bound the spectrum   */
   int32_t warm_start;        /* 1: evecs holds the start block V0 on entry      */
   uint64_t seed;             /* random start block / Lanczos vector otherwise   */
-  int32_t lanczos_steps;     /* default 40                                      */
-  const void *lanczos_v0;    /* optional device vector of length N              */
+  int32_t lanczos_steps;     /* steps per Lanczos run, default 40               */
+  int32_t lanczos_nvec;      /* independent Lanczos runs, 1..8, default 4       */
+  const void *lanczos_v0;    /* optional device start vectors: N x lanczos_nvec,
+                                column-major, leading dimension N               */
   int32_t inject_chol_fail_iter; /* test hook: the Cholesky of this iteration
                                     reports failure (-1 = off)                  */
   double mixed_switch;       /* MIXED: switch the filter to FP64 once the lowest
@@ -229,12 +231,37 @@ chase_status chase_residuals(chase_dtype dtype, const void *HV, int64_t ldhv, co
                              int64_t ldv, int64_t N, int32_t ncols, const double *ritz,
                              double *resid, void *stream);
 
-/* Spectral bounds by Lanczos with full reorthogonalisation from the device
- * vector v0 (length N): alpha, beta (host [steps]) are T_k's coefficients,
- * bounds (host [3]) = (lambda_1, lambda_l, upper) estimates for l = nsearch. */
+/* Spectral bounds for the filter interval (Alg. 1 and Sec. 1.2: only the
+ * estimate of lambda_n has to bound the spectrum from above).  nvec
+ * independent Lanczos runs of min(steps, N) steps, each with full
+ * reorthogonalisation, from the columns of the device block V0 (N x nvec,
+ * column-major, leading dimension N, 1 <= nvec <= 8; the runs normalise
+ * their start vectors).  H is the device matrix (N x N, column-major, ldh).
+ * Host outputs: alpha, beta [nvec * steps], run r's T_k coefficients at
+ * [r * steps, r * steps + k) (beta_j couples steps j and j + 1; the last one
+ * is the final residual norm), zero past k; bounds [3] = (lambda_1 estimate,
+ * lambda_l estimate for l = nsearch, upper bound):
+ *   upper    = max over runs of theta_max + 2 |beta_k| |e_k^T s_max| (the
+ *              largest Ritz value of T_k plus twice its Ritz pair's residual)
+ *   lambda_1 = smallest Ritz value over the runs
+ *   lambda_l = the Ritz value where the run-averaged spectral-density count
+ *              sum over Ritz values <= x of N |e_1^T s_j|^2 first reaches l,
+ *              clamped to [lambda_1 + 1e-3 w, upper - 1e-3 w], w = upper - lambda_1.
+ * Work is enqueued on `stream` (NULL: the library's) and the call returns
+ * after it has finished.  Errors: EINVAL for NULL pointers or invalid sizes;
+ * EDEVICE / ENOMEM as for the other calls. */
 chase_status chase_lanczos(chase_dtype dtype, const void *H, int64_t N, int64_t ldh,
-                           const void *v0, int32_t steps, int32_t nsearch, double *alpha,
-                           double *beta, double *bounds, void *stream);
+                           const void *V0, int32_t nvec, int32_t steps, int32_t nsearch,
+                           double *alpha, double *beta, double *bounds, void *stream);
+
+/* The bounds of chase_lanczos from coefficients computed elsewhere (host
+ * only, no device work): alpha, beta [nvec * steps] hold run r's T_k at
+ * [r * steps, r * steps + steps) in the layout chase_lanczos returns (a run
+ * whose beta_j is zero ends at step j); N is the matrix order, bounds [3] as
+ * for chase_lanczos.  Errors: EINVAL for NULL pointers, nvec or steps < 1,
+ * or nsearch outside 1..N. */
+chase_status chase_lanczos_bounds(const double *alpha, const double *beta, int32_t nvec,
+                                  int32_t steps, int64_t N, int32_t nsearch, double *bounds);
 
 const char *chase_strerror(chase_status s);
 const char *chase_last_error(void);

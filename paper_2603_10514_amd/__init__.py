@@ -4,7 +4,7 @@ Argument marshalling only: every step of the solver runs in the HIP library.
 Device buffers are torch tensors on the GPU (column-major: stride(0) == 1);
 they are passed as raw pointers together with torch's current stream, so the
 library's work is ordered after torch's.  Importing this package raises if
-libchase.so has not been built (python -m paper_2603_10514_amd.build).
+libchase.so has not been built (python paper_2603_10514_amd/build.py).
 """
 import ctypes
 import os
@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchase.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libchase.so is not built; run `python -m paper_2603_10514_amd.build` "
+    raise ImportError("libchase.so is not built; run `python paper_2603_10514_amd/build.py` "
                       "(the solver has no fallback path)")
 lib = ctypes.CDLL(LIB_PATH)
 
@@ -58,7 +58,8 @@ class ChaseOpts(ctypes.Structure):
                 ("lambda_1", ctypes.c_double), ("lambda_l", ctypes.c_double),
                 ("lambda_max", ctypes.c_double), ("warm_start", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("lanczos_steps", ctypes.c_int32),
-                ("lanczos_v0", ctypes.c_void_p), ("inject_chol_fail_iter", ctypes.c_int32),
+                ("lanczos_nvec", ctypes.c_int32), ("lanczos_v0", ctypes.c_void_p),
+                ("inject_chol_fail_iter", ctypes.c_int32),
                 ("mixed_switch", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("log_cb", LOG_CB), ("log_user", ctypes.c_void_p),
                 ("block_cb", BLOCK_CB), ("block_user", ctypes.c_void_p)]
@@ -112,8 +113,9 @@ _sig("chase_qr_factor", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _i32, ctype
 _sig("chase_rayleigh_ritz", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i64, _i32, _dp,
                                            _p, _i64, _p, _i64, _p])
 _sig("chase_residuals", ctypes.c_int, [ctypes.c_int, _p, _i64, _p, _i64, _i64, _i32, _dp, _dp, _p])
-_sig("chase_lanczos", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i32, _i32, _dp, _dp, _dp,
-                                     _p])
+_sig("chase_lanczos", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i32, _i32, _i32, _dp, _dp,
+                                     _dp, _p])
+_sig("chase_lanczos_bounds", ctypes.c_int, [_dp, _dp, _i32, _i32, _i64, _i32, _dp])
 _sig("chase_strerror", ctypes.c_char_p, [ctypes.c_int])
 _sig("chase_last_error", ctypes.c_char_p, [])
 
@@ -339,18 +341,37 @@ def chase_residuals(HV, V, ritz, stream=None):
     return out
 
 
-def chase_lanczos(H, v0, steps, nsearch, stream=None):
+def chase_lanczos(H, V0, steps, nsearch, stream=None):
+    """Lanczos runs from the columns of the device block V0 (N, or N x nvec
+    column-major).  Returns (alpha, beta) as nvec x k arrays, k = min(steps,
+    N), and the bounds (lambda_1, lambda_l, upper)."""
     N = H.shape[0]
     hp, ldh = _hermitian_ptr(H)
-    a = np.zeros(steps)
-    b = np.zeros(steps)
+    nvec = 1 if V0.dim() == 1 else V0.shape[1]
+    if V0.shape[0] != N or (V0.dim() == 2 and nvec > 1 and V0.stride() != (1, N)):
+        raise ValueError("V0 must be N x nvec, column-major with leading dimension N")
+    a = np.zeros(nvec * steps)
+    b = np.zeros(nvec * steps)
     bounds = np.zeros(3)
-    st = lib.chase_lanczos(_dtype_code(H), hp, N, ldh, v0.data_ptr(), steps, nsearch,
+    st = lib.chase_lanczos(_dtype_code(H), hp, N, ldh, V0.data_ptr(), nvec, steps, nsearch,
                            a.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
                            bounds.ctypes.data_as(_dp), _stream_ptr(stream))
     _check(st, "chase_lanczos")
     k = min(steps, N)
-    return a[:k], b[:k], tuple(bounds)
+    return a.reshape(nvec, steps)[:, :k], b.reshape(nvec, steps)[:, :k], tuple(bounds)
+
+
+def chase_lanczos_bounds(alpha, beta, N, nsearch):
+    """Bounds from Lanczos coefficients (nvec x steps arrays; host only)."""
+    a = np.ascontiguousarray(np.atleast_2d(alpha), dtype=np.float64)
+    b = np.ascontiguousarray(np.atleast_2d(beta), dtype=np.float64)
+    if a.shape != b.shape:
+        raise ValueError("alpha and beta must have the same shape")
+    bounds = np.zeros(3)
+    st = lib.chase_lanczos_bounds(a.ctypes.data_as(_dp), b.ctypes.data_as(_dp), a.shape[0],
+                                  a.shape[1], N, nsearch, bounds.ctypes.data_as(_dp))
+    _check(st, "chase_lanczos_bounds")
+    return tuple(bounds)
 
 
 # ------------------------------------------------------ async handles -----

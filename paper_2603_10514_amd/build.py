@@ -1,6 +1,9 @@
 """Build libchase.so (the gfx950 HIP library behind include/chase.h) in place.
 
-    python -m paper_2603_10514_amd.build        (or build() from Python)
+    python paper_2603_10514_amd/build.py        (or __graft_entry__.build())
+
+(Run as a script: `python -m` would import the package, which loads the
+previous libchase.so.)
 
 Compiles every source under csrc/ with hipcc for gfx950 and links rocSOLVER
 and rocBLAS.  Always recompiles; the output lands next to this file."""

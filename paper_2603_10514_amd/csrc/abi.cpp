@@ -71,6 +71,8 @@ chase_status check_opts(const chase_opts *o) {
     return fail(CHASE_EINVAL, "need lambda_1 <= lambda_l < lambda_max");
   if (!o->have_bounds && o->lanczos_steps < 1)
     return fail(CHASE_EINVAL, "lanczos_steps must be >= 1");
+  if (!o->have_bounds && (o->lanczos_nvec < 1 || o->lanczos_nvec > 8))
+    return fail(CHASE_EINVAL, "lanczos_nvec must be in 1..8");
   return CHASE_OK;
 }
 
@@ -111,6 +113,7 @@ void chase_opts_default(chase_opts *o) {
   o->est_lo = 20.0;
   o->seed = 1;
   o->lanczos_steps = 40;
+  o->lanczos_nvec = 4;
   o->inject_chol_fail_iter = -1;
   o->mixed_switch = 6e-5;
 }
@@ -143,7 +146,7 @@ chase_status chase_solve(const void *H, int64_t N, int64_t ldh, int32_t nev, int
 size_t chase_workspace_bytes(int64_t N, int32_t nev, int32_t nex, chase_dtype dtype,
                              chase_precision precision) {
   if (N < 2 || nev < 1 || nex < 1 || (int64_t)nev + nex > N) return 0;
-  return work_bytes(N, nev + nex, dtype == CHASE_COMPLEX128, precision == CHASE_PREC_MIXED, 40);
+  return work_bytes(N, nev + nex, dtype == CHASE_COMPLEX128, precision == CHASE_PREC_MIXED, 40, 4);
 }
 
 chase_status chase_handle_create(int64_t N_max, int32_t nev_max, int32_t nex_max,
@@ -164,7 +167,8 @@ chase_status chase_handle_create(int64_t N_max, int32_t nev_max, int32_t nex_max
       h->ctx.ensure_init();
       h->ctx.ensure_work(N_max, h->L_max, opts->dtype == CHASE_COMPLEX128,
                          opts->precision == CHASE_PREC_MIXED,
-                         opts->have_bounds ? 0 : std::max(1, opts->lanczos_steps));
+                         opts->have_bounds ? 0 : std::max(1, opts->lanczos_steps),
+                         std::max(1, opts->lanczos_nvec));
     } catch (...) {
       h->ctx.release();
       delete h;
@@ -349,28 +353,46 @@ chase_status chase_residuals(chase_dtype dtype, const void *HV, int64_t ldhv, co
 }
 
 chase_status chase_lanczos(chase_dtype dtype, const void *H, int64_t N, int64_t ldh,
-                           const void *v0, int32_t steps, int32_t nsearch, double *alpha,
-                           double *beta, double *bounds, void *stream) {
-  if (!H || !v0 || !alpha || !beta || !bounds) return fail(CHASE_EINVAL, "NULL argument");
+                           const void *V0, int32_t nvec, int32_t steps, int32_t nsearch,
+                           double *alpha, double *beta, double *bounds, void *stream) {
+  if (!H || !V0 || !alpha || !beta || !bounds) return fail(CHASE_EINVAL, "NULL argument");
   if (N < 1 || ldh < N || steps < 1 || nsearch < 1 || nsearch > N)
     return fail(CHASE_EINVAL, "invalid sizes");
+  if (nvec < 1 || nvec > 8) return fail(CHASE_EINVAL, "nvec must be in 1..8");
   return guarded([&] {
     const bool cplx = dtype == CHASE_COMPLEX128;
     Ctx &cx = thread_ctx();
-    cx.ensure_work(N, std::max(1, nsearch), cplx, false, steps);
+    cx.ensure_work(N, std::max(1, nsearch), cplx, false, steps, nvec);
     hipStream_t own = cx.stream;
     cx.stream = stream ? (hipStream_t)stream : own;
     std::vector<double> a, b;
     try {
-      lanczos(cx, cplx, H, ldh, N, v0, steps, 0, a, b);
+      lanczos(cx, cplx, H, ldh, N, V0, nvec, steps, 0, a, b);
     } catch (...) {
       cx.stream = own;
       throw;
     }
     cx.stream = own;
-    const int k = (int)a.size();
-    for (int j = 0; j < k; ++j) { alpha[j] = a[j]; beta[j] = b[j]; }
-    lanczos_bounds_from_tridiag(a, b, N, nsearch, bounds);
+    const int k = (int)a.size() / nvec;
+    for (int r = 0; r < nvec; ++r)
+      for (int j = 0; j < steps; ++j) {
+        alpha[(size_t)r * steps + j] = j < k ? a[(size_t)r * k + j] : 0.0;
+        beta[(size_t)r * steps + j] = j < k ? b[(size_t)r * k + j] : 0.0;
+      }
+    lanczos_bounds_from_runs(a, b, nvec, N, nsearch, bounds);
+    return CHASE_OK;
+  });
+}
+
+chase_status chase_lanczos_bounds(const double *alpha, const double *beta, int32_t nvec,
+                                  int32_t steps, int64_t N, int32_t nsearch, double *bounds) {
+  if (!alpha || !beta || !bounds) return fail(CHASE_EINVAL, "NULL argument");
+  if (nvec < 1 || steps < 1 || N < 1 || nsearch < 1 || nsearch > N)
+    return fail(CHASE_EINVAL, "invalid sizes");
+  return guarded([&] {
+    std::vector<double> a(alpha, alpha + (size_t)nvec * steps);
+    std::vector<double> b(beta, beta + (size_t)nvec * steps);
+    lanczos_bounds_from_runs(a, b, nvec, N, nsearch, bounds);
     return CHASE_OK;
   });
 }

@@ -217,34 +217,129 @@ __global__ void k_randn(E *V, int64_t ldv, int n, uint64_t seed) {
 }
 
 // ----------------------------------------------------- Lanczos helpers --
+// ------------------------------------------------- block matrix-vector --
+// Partial sums of y = A X for a column-major A (M x K, lda) and a block X of
+// NV right-hand sides (K x NV, ldx).  The work is HBM-bound: every element
+// of A is loaded once.  A work-group of 256 threads owns RPT * 256 rows (row
+// r0 + t + 256 q for thread t) and the column range [c0, c0 + kchunk) of
+// split blockIdx.y; each column's slice of A is one coalesced load per wave,
+// X's rows are staged in LDS and broadcast.  The split's sums go to
+// P + blockIdx.y * sstride (M x NV, leading dimension ldp).
+template <typename E, int NV, int RPT>
+__global__ __launch_bounds__(256) void k_gemv_cm(const E *__restrict__ A, int64_t lda, int M,
+                                                 int K, const E *__restrict__ X, int64_t ldx,
+                                                 int kchunk, E *__restrict__ P, int64_t ldp,
+                                                 int64_t sstride) {
+  constexpr int CB = 64, U = 8;
+  __shared__ E xs[CB][NV];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 256 * RPT + t;
+  const int c0 = blockIdx.y * kchunk;
+  const int c1 = min(K, c0 + kchunk);
+  E acc[RPT][NV];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[q][v] = Num<E>::zero();
+  bool ok[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) ok[q] = r0 + 256 * q < M;
+  for (int cb = c0; cb < c1; cb += CB) {
+    const int nc = min(CB, c1 - cb);
+    __syncthreads();
+    for (int e = t; e < nc * NV; e += 256) {
+      const int j = e / NV, v = e % NV;
+      xs[j][v] = X[(int64_t)(cb + j) + v * ldx];
+    }
+    __syncthreads();
+    int j0 = 0;
+    for (; j0 + U <= nc; j0 += U) {
+      E a[U][RPT];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const E *col = A + (int64_t)(cb + j0 + u) * lda + r0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) a[u][q] = ok[q] ? col[256 * q] : Num<E>::zero();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[q][v] = acc[q][v] + Num<E>::mul(a[u][q], xs[j0 + u][v]);
+    }
+    for (; j0 < nc; ++j0) {
+      const E *col = A + (int64_t)(cb + j0) * lda + r0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const E a = ok[q] ? col[256 * q] : Num<E>::zero();
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[q][v] = acc[q][v] + Num<E>::mul(a, xs[j0][v]);
+      }
+    }
+  }
+  E *out = P + blockIdx.y * sstride;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+    if (ok[q])
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[r0 + 256 * q + v * ldp] = acc[q][v];
+}
+
+// y[:, v] = sum over nsplit partials (each M x nv, leading dimension M).
 template <typename E>
-__global__ __launch_bounds__(256) void k_dot_re(const E *v, const E *w, int n, double *out) {
+__global__ void k_gemv_reduce(const E *P, int nsplit, int64_t sstride, int M, E *Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const int v = blockIdx.y;
+  E s = Num<E>::zero();
+  for (int q = 0; q < nsplit; ++q) s = s + P[q * sstride + (int64_t)v * M + i];
+  Y[i + v * ldy] = s;
+}
+
+// out[c] = Re(v_c^H w_c) for the ncols columns (one work-group per column).
+template <typename E>
+__global__ __launch_bounds__(256) void k_dot_re_cols(const E *v, const E *w, int64_t ld, int n,
+                                                     double *out) {
   __shared__ double sh[256];
+  const E *a = v + blockIdx.x * ld;
+  const E *b = w + blockIdx.x * ld;
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += 256)
-    s += Num<E>::re(v[i]) * Num<E>::re(w[i]) + Num<E>::im(v[i]) * Num<E>::im(w[i]);
+    s += Num<E>::re(a[i]) * Num<E>::re(b[i]) + Num<E>::im(a[i]) * Num<E>::im(b[i]);
   s = block_sum256(s, sh);
-  if (threadIdx.x == 0) *out = s;
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
+// beta[c] = ||w_c||, vout_c = w_c / beta[c] (zero when beta[c] = 0).
 template <typename E>
-__global__ __launch_bounds__(256) void k_norm_scale(const E *w, int n, E *vout, double *beta) {
+__global__ __launch_bounds__(256) void k_norm_scale_cols(const E *w, int64_t ldw, int n, E *vout,
+                                                         int64_t ldo, double *beta) {
   __shared__ double sh[256];
+  const E *a = w + blockIdx.x * ldw;
+  E *o = vout + blockIdx.x * ldo;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += Num<E>::abs2(w[i]);
+  for (int i = threadIdx.x; i < n; i += 256) s += Num<E>::abs2(a[i]);
   s = sqrt(block_sum256(s, sh));
   const double inv = s > 0.0 ? 1.0 / s : 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) vout[i] = Num<E>::scale(w[i], inv);
-  if (threadIdx.x == 0 && beta) *beta = s;
+  for (int i = threadIdx.x; i < n; i += 256) o[i] = Num<E>::scale(a[i], inv);
+  if (threadIdx.x == 0) beta[blockIdx.x] = s;
 }
 
+// out (rows x nv, leading dimension ldo) = sum over nsplit partials (each
+// rows x nv, leading dimension ldp), keeping only the entries of row q in
+// column q % nv and zeroing the others: the coefficients of each Lanczos run
+// against its own basis vectors when the runs' bases are interleaved.
 template <typename E>
-__global__ void k_sum_splits(const E *P, int nsplit, int64_t sstride, int nelem, E *out) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= nelem) return;
+__global__ void k_sum_splits_diag(const E *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
+                                  int nv, E *out, int64_t ldo) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= rows) return;
+  const int c = blockIdx.y;
   E s = Num<E>::zero();
-  for (int q = 0; q < nsplit; ++q) s = s + P[q * sstride + i];
-  out[i] = s;
+  if (q % nv == c)
+    for (int p = 0; p < nsplit; ++p) s = s + P[p * sstride + (int64_t)c * ldp + q];
+  out[(int64_t)c * ldo + q] = s;
 }
 
 // ========================================================== launchers ==
@@ -350,33 +445,96 @@ void randn(bool cplx, void *V, int64_t ldv, int n, int ncols, uint64_t seed, hip
     hipLaunchKernelGGL(k_randn<double>, grid, dim3(256), 0, s, (double *)V, ldv, n, seed);
 }
 
-void dot_re(bool cplx, const void *v, const void *w, int n, double *out, hipStream_t s) {
-  if (cplx)
-    hipLaunchKernelGGL(k_dot_re<double2>, dim3(1), dim3(256), 0, s, (const double2 *)v,
-                       (const double2 *)w, n, out);
-  else
-    hipLaunchKernelGGL(k_dot_re<double>, dim3(1), dim3(256), 0, s, (const double *)v,
-                       (const double *)w, n, out);
+template <typename E, int NV>
+static void gemv_launch(const E *A, int64_t lda, int M, int K, const E *X, int64_t ldx, E *Y,
+                        int64_t ldy, void *scratch, size_t scratch_bytes, hipStream_t s) {
+  constexpr int RPT = sizeof(E) == 16 ? 2 : 4;
+  const int rb = (M + 256 * RPT - 1) / (256 * RPT);
+  // enough work-groups to keep every CU streaming, limited by the scratch
+  // that holds one M x NV partial per split and by 64 columns per split
+  const size_t per = sizeof(E) * (size_t)M * NV;
+  int S = (2048 + rb - 1) / rb;
+  S = (int)std::min<int64_t>(S, (K + 63) / 64);
+  S = (int)std::min<size_t>((size_t)S, scratch_bytes / per);
+  if (S <= 1) {
+    hipLaunchKernelGGL((k_gemv_cm<E, NV, RPT>), dim3(rb, 1), dim3(256), 0, s, A, lda, M, K, X, ldx,
+                       K, Y, ldy, (int64_t)0);
+    return;
+  }
+  int kchunk = (K + S - 1) / S;
+  kchunk = (kchunk + 7) / 8 * 8;
+  S = (K + kchunk - 1) / kchunk;
+  E *P = (E *)scratch;
+  hipLaunchKernelGGL((k_gemv_cm<E, NV, RPT>), dim3(rb, S), dim3(256), 0, s, A, lda, M, K, X, ldx,
+                     kchunk, P, (int64_t)M, (int64_t)M * NV);
+  hipLaunchKernelGGL(k_gemv_reduce<E>, dim3(blocks(M, 256), NV), dim3(256), 0, s, (const E *)P, S,
+                     (int64_t)M * NV, M, Y, ldy);
 }
 
-void norm_scale(bool cplx, const void *w, int n, void *vout, double *beta_out, hipStream_t s) {
-  if (cplx)
-    hipLaunchKernelGGL(k_norm_scale<double2>, dim3(1), dim3(256), 0, s, (const double2 *)w, n,
-                       (double2 *)vout, beta_out);
-  else
-    hipLaunchKernelGGL(k_norm_scale<double>, dim3(1), dim3(256), 0, s, (const double *)w, n,
-                       (double *)vout, beta_out);
+template <typename E>
+static void gemv_nv(const E *A, int64_t lda, int M, int K, const E *X, int64_t ldx, int nv, E *Y,
+                    int64_t ldy, void *scratch, size_t scratch_bytes, hipStream_t s) {
+  switch (nv) {
+    case 1: gemv_launch<E, 1>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    case 2: gemv_launch<E, 2>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    case 3: gemv_launch<E, 3>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    case 4: gemv_launch<E, 4>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    case 5: gemv_launch<E, 5>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    case 6: gemv_launch<E, 6>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    case 7: gemv_launch<E, 7>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    case 8: gemv_launch<E, 8>(A, lda, M, K, X, ldx, Y, ldy, scratch, scratch_bytes, s); break;
+    default: throw InvalidArg();
+  }
 }
 
-void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int nelem, void *out,
+void gemv_block(bool cplx, const void *A, int64_t lda, int M, int K, const void *X, int64_t ldx,
+                int nv, void *Y, int64_t ldy, void *scratch, size_t scratch_bytes,
                 hipStream_t s) {
-  if (nelem <= 0) return;
+  if (M <= 0 || nv <= 0) return;
+  if (K <= 0) {
+    fill_zero(cplx, Y, ldy, M, nv, s);
+    return;
+  }
   if (cplx)
-    hipLaunchKernelGGL(k_sum_splits<double2>, dim3(blocks(nelem, 256)), dim3(256), 0, s,
-                       (const double2 *)P, nsplit, sstride, nelem, (double2 *)out);
+    gemv_nv<double2>((const double2 *)A, lda, M, K, (const double2 *)X, ldx, nv, (double2 *)Y,
+                     ldy, scratch, scratch_bytes, s);
   else
-    hipLaunchKernelGGL(k_sum_splits<double>, dim3(blocks(nelem, 256)), dim3(256), 0, s,
-                       (const double *)P, nsplit, sstride, nelem, (double *)out);
+    gemv_nv<double>((const double *)A, lda, M, K, (const double *)X, ldx, nv, (double *)Y, ldy,
+                    scratch, scratch_bytes, s);
+}
+
+void dot_re_cols(bool cplx, const void *v, const void *w, int64_t ld, int n, int ncols,
+                 double *out, hipStream_t s) {
+  if (ncols <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(k_dot_re_cols<double2>, dim3(ncols), dim3(256), 0, s, (const double2 *)v,
+                       (const double2 *)w, ld, n, out);
+  else
+    hipLaunchKernelGGL(k_dot_re_cols<double>, dim3(ncols), dim3(256), 0, s, (const double *)v,
+                       (const double *)w, ld, n, out);
+}
+
+void norm_scale_cols(bool cplx, const void *w, int64_t ldw, int n, int ncols, void *vout,
+                     int64_t ldo, double *beta, hipStream_t s) {
+  if (ncols <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(k_norm_scale_cols<double2>, dim3(ncols), dim3(256), 0, s,
+                       (const double2 *)w, ldw, n, (double2 *)vout, ldo, beta);
+  else
+    hipLaunchKernelGGL(k_norm_scale_cols<double>, dim3(ncols), dim3(256), 0, s, (const double *)w,
+                       ldw, n, (double *)vout, ldo, beta);
+}
+
+void sum_splits_diag(bool cplx, const void *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
+                     int nv, void *out, int64_t ldo, hipStream_t s) {
+  if (rows <= 0 || nv <= 0) return;
+  dim3 grid(blocks(rows, 256), nv);
+  if (cplx)
+    hipLaunchKernelGGL(k_sum_splits_diag<double2>, grid, dim3(256), 0, s, (const double2 *)P,
+                       nsplit, sstride, ldp, rows, nv, (double2 *)out, ldo);
+  else
+    hipLaunchKernelGGL(k_sum_splits_diag<double>, grid, dim3(256), 0, s, (const double *)P, nsplit,
+                       sstride, ldp, rows, nv, (double *)out, ldo);
 }
 
 // ------------------------------------------------------------- GEMM ------

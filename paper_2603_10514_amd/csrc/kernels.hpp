@@ -46,10 +46,18 @@ void convert_to32(bool cplx, const void *src, int64_t lds, void *dst, int64_t ld
                   int cols, hipStream_t s);
 // Gaussian block: real N(0,1); complex (N(0,1) + i N(0,1)) / sqrt(2).
 void randn(bool cplx, void *V, int64_t ldv, int n, int ncols, uint64_t seed, hipStream_t s);
-// Lanczos helpers (single work-group reductions).
-void dot_re(bool cplx, const void *v, const void *w, int n, double *out, hipStream_t s);
-void norm_scale(bool cplx, const void *w, int n, void *vout, double *beta_out, hipStream_t s);
-void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int nelem, void *out,
-                hipStream_t s);
+// Lanczos helpers.  Y (M x nv, ldy) = A (M x K, column-major, lda) X (K x nv, ldx), 1 <= nv <= 8,
+// streaming A once; column-split partials use `scratch` (scratch_bytes).
+void gemv_block(bool cplx, const void *A, int64_t lda, int M, int K, const void *X, int64_t ldx,
+                int nv, void *Y, int64_t ldy, void *scratch, size_t scratch_bytes, hipStream_t s);
+// out[c] = Re(v_c^H w_c); beta[c] = ||w_c|| and vout_c = w_c / beta[c]
+// (one work-group per column).
+void dot_re_cols(bool cplx, const void *v, const void *w, int64_t ld, int n, int ncols,
+                 double *out, hipStream_t s);
+void norm_scale_cols(bool cplx, const void *w, int64_t ldw, int n, int ncols, void *vout,
+                     int64_t ldo, double *beta, hipStream_t s);
+// out (rows x nv) = sum of nsplit partials, keeping row q only in column q % nv.
+void sum_splits_diag(bool cplx, const void *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
+                     int nv, void *out, int64_t ldo, hipStream_t s);
 
 }  // namespace chase

@@ -110,33 +110,49 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w,
   V.swap(Vs);
 }
 
-// Bounds from the Lanczos tridiagonal T_k: upper = largest Ritz value +
-// |beta_k|; lambda_1 estimate = smallest Ritz value; lambda_l estimate = the
-// Ritz value where the spectral-density count N |s_1j|^2 first reaches l,
-// clamped into the interval.
-void lanczos_bounds_from_tridiag(const std::vector<double> &alpha, const std::vector<double> &beta,
-                                 int64_t N, int nsearch, double bounds[3]) {
-  int k = (int)alpha.size();
-  for (int j = 0; j < k; ++j)
-    if (beta[j] == 0.0) { k = j + 1; break; }
-  std::vector<double> T((size_t)k * k, 0.0), w, V;
-  for (int j = 0; j < k; ++j) {
-    T[(size_t)j * k + j] = alpha[j];
-    if (j + 1 < k) {
-      T[(size_t)j * k + j + 1] = beta[j];
-      T[(size_t)(j + 1) * k + j] = beta[j];
+// Bounds from nvec Lanczos runs (Sec. 1.2 needs only the upper end to bound
+// the spectrum): upper = max over runs of the largest Ritz value of T_k plus
+// twice the residual norm |beta_k| |e_k^T s_max| of its Ritz pair; lambda_1
+// estimate = smallest Ritz value over the runs; lambda_l estimate = the Ritz
+// value where the spectral-density count, (1/nvec) sum over runs and Ritz
+// values <= x of N |e_1^T s_j|^2, first reaches l, clamped into the
+// interval.  A run whose Krylov space became invariant (a zero beta) ends
+// there.
+void lanczos_bounds_from_runs(const std::vector<double> &alpha, const std::vector<double> &beta,
+                              int nvec, int64_t N, int nsearch, double bounds[3]) {
+  const int kmax = (int)alpha.size() / nvec;
+  std::vector<std::pair<double, double>> dos;  // (Ritz value, weight)
+  double low = INFINITY, up = -INFINITY;
+  for (int r = 0; r < nvec; ++r) {
+    const double *a = alpha.data() + (size_t)r * kmax;
+    const double *b = beta.data() + (size_t)r * kmax;
+    int k = kmax;
+    for (int j = 0; j < kmax; ++j)
+      if (b[j] == 0.0) { k = j + 1; break; }
+    std::vector<double> T((size_t)k * k, 0.0), w, V;
+    for (int j = 0; j < k; ++j) {
+      T[(size_t)j * k + j] = a[j];
+      if (j + 1 < k) {
+        T[(size_t)j * k + j + 1] = b[j];
+        T[(size_t)(j + 1) * k + j] = b[j];
+      }
     }
+    jacobi_eig(k, T, w, V);  // V[i * k + j]: component i of eigenvector j
+    const double top_resid = std::fabs(b[k - 1]) * std::fabs(V[(size_t)(k - 1) * k + (k - 1)]);
+    up = std::max(up, w[k - 1] + 2.0 * top_resid);
+    low = std::min(low, w[0]);
+    for (int j = 0; j < k; ++j) dos.push_back({w[j], (double)N * V[j] * V[j] / nvec});
   }
-  jacobi_eig(k, T, w, V);
-  const double up = w[k - 1] + std::fabs(beta[k - 1]);
-  const double low = w[0];
+  std::stable_sort(dos.begin(), dos.end(),
+                   [](const std::pair<double, double> &x, const std::pair<double, double> &y) {
+                     return x.first < y.first;
+                   });
   double cum = 0.0;
-  int idx = k - 1;
-  for (int j = 0; j < k; ++j) {
-    cum += (double)N * V[j] * V[j];  // first row of the eigenvector matrix
-    if (cum >= (double)nsearch) { idx = j; break; }
+  double mid = dos.back().first;
+  for (const auto &d : dos) {
+    cum += d.second;
+    if (cum >= (double)nsearch) { mid = d.first; break; }
   }
-  double mid = w[idx];
   const double span = up - low;
   mid = std::min(std::max(mid, low + 1e-3 * span), up - 1e-3 * span);
   bounds[0] = low;
@@ -165,7 +181,7 @@ struct Layout {
   size_t total;
 };
 
-static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
+static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int nv) {
   const size_t es = cplx ? 16 : 8;
   const int ns = gram_splits(N, L);
   const int lzs = lz_splits(N);
@@ -178,11 +194,11 @@ static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
       al(16), al(4 * (size_t)L), al(4 * (size_t)L), al(16),              // flag deg perm rinfo
       al(es * L),                                                         // tau
       mixed ? al(es / 2 * (size_t)N * N) : 0,                             // H32
-      k ? al(es * (size_t)N * (k + 1)) : 0,                               // LV
-      k ? al(es * (size_t)N) : 0,                                         // LW
-      k ? al(es * (size_t)k) : 0,                                         // Lh
-      k ? al(es * (size_t)lzs * k) : 0,                                   // LhP
-      k ? al(16 * (size_t)k) : 0,                                         // lz_ab
+      k ? al(es * (size_t)N * (k + 1) * nv) : 0,                          // LV
+      k ? al(es * (size_t)N * nv) : 0,                                    // LW
+      k ? al(es * (size_t)k * nv * nv) : 0,                               // Lh
+      k ? al(es * (size_t)lzs * k * nv * nv) : 0,                         // LhP
+      k ? al(16 * (size_t)k * nv) : 0,                                    // lz_ab
       al(kTailScratch),                                                   // SK
   };
   Layout lo{};
@@ -196,8 +212,8 @@ static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
   return lo;
 }
 
-size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
-  return layout(N, L, cplx, mixed, lz_steps).total;
+size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec) {
+  return layout(N, L, cplx, mixed, lz_steps, lz_nvec).total;
 }
 
 void Ctx::ensure_init() {
@@ -221,12 +237,12 @@ void Ctx::set_stream(hipStream_t s) {
   rocblas_set_stream(rb, target);
 }
 
-void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
+void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec) {
   ensure_init();
   if (w.base && w.N == N && w.L == L && w.cplx == cplx && w.mixed == mixed &&
-      w.lz_steps == lz_steps)
+      w.lz_steps == lz_steps && w.lz_nvec == lz_nvec)
     return;
-  Layout lo = layout(N, L, cplx, mixed, lz_steps);
+  Layout lo = layout(N, L, cplx, mixed, lz_steps, lz_nvec);
   if (w.base == nullptr || w.bytes < lo.total) {
     if (w.base) {
       CHASE_HIP(hipStreamSynchronize(stream));
@@ -248,6 +264,7 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
   w.cplx = cplx;
   w.mixed = mixed;
   w.lz_steps = lz_steps;
+  w.lz_nvec = lz_nvec;
   w.nsplit = gram_splits(N, L);
   w.lz_split = lz_splits(N);
   char *b = w.base;
@@ -267,11 +284,12 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps) {
   w.SK = b + lo.off[i++];
   w.sk_bytes = kTailScratch;
   // pinned host mirrors, grown on demand
-  if (L > h_cap_L || std::max(lz_steps, 1) > h_cap_lz) {
+  const int lz_cols = std::max(lz_steps, 1) * std::max(lz_nvec, 1);
+  if (L > h_cap_L || lz_cols > h_cap_lz) {
     CHASE_HIP(hipStreamSynchronize(stream));
     free_pinned();
     h_cap_L = std::max(L, h_cap_L);
-    h_cap_lz = std::max(std::max(lz_steps, 1), h_cap_lz);
+    h_cap_lz = std::max(lz_cols, h_cap_lz);
     CHASE_HIP(hipHostMalloc((void **)&w.h_theta, 8 * (size_t)h_cap_L));
     CHASE_HIP(hipHostMalloc((void **)&w.h_resid, 8 * (size_t)h_cap_L));
     CHASE_HIP(hipHostMalloc((void **)&w.h_ab, 16 * (size_t)h_cap_lz));
@@ -553,56 +571,64 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
   CHASE_HIP(hipGetLastError());
 }
 
-// k Lanczos steps with full reorthogonalisation (classical Gram-Schmidt,
-// twice); alpha/beta returned on the host.
-void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *v0, int steps,
-             uint64_t seed, std::vector<double> &alpha, std::vector<double> &beta) {
+// nvec independent Lanczos runs of k steps, each with full
+// reorthogonalisation against its own basis (classical Gram-Schmidt, twice),
+// advanced together so that every step streams H once for all of them.  The
+// runs' basis vectors are interleaved step by step: column j * nvec + r of LV
+// is run r's j-th vector, so the first (j + 1) nvec columns are every run's
+// basis so far.  Run r's coefficients come back on the host at
+// alpha/beta[r * k + j].
+void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *V0, int nvec,
+             int steps, uint64_t seed, std::vector<double> &alpha, std::vector<double> &beta) {
   Work &w = c.w;
   const int k = (int)std::min<int64_t>(steps, N);
+  const int nv = nvec;
   const size_t es = cplx ? 16 : 8;
   const int nsl = lz_splits(N);
   const int bk = gemm_bk();
-  if (v0)
-    CHASE_HIP(hipMemcpyAsync(w.LW, v0, es * N, hipMemcpyDeviceToDevice, c.stream));
+  const int64_t ldh_ = k * nv;  // leading dimension of the coefficient blocks
+  if (V0)
+    CHASE_HIP(hipMemcpyAsync(w.LW, V0, es * N * nv, hipMemcpyDeviceToDevice, c.stream));
   else
-    randn(cplx, w.LW, N, (int)N, 1, seed, c.stream);
-  norm_scale(cplx, w.LW, (int)N, w.LV, nullptr, c.stream);
+    randn(cplx, w.LW, N, (int)N, nv, seed, c.stream);
+  norm_scale_cols(cplx, w.LW, N, (int)N, nv, w.LV, N, w.lz_ab + (size_t)k * nv, c.stream);
   for (int j = 0; j < k; ++j) {
-    void *vj = (char *)w.LV + es * (size_t)N * j;
-    {
-      GemmArgs a = bigargs(c);
-      a.A = H; a.lda = ldh;
-      a.B = vj; a.ldb = N;
-      a.M = (int)N; a.N = 1; a.K = (int)N;
-      a.C = w.LW; a.ldc = N;
-      gemm(cplx, false, true, false, false, GEMM_BIG, a, 1, c.stream);
-    }
-    dot_re(cplx, vj, w.LW, (int)N, w.lz_ab + j, c.stream);
+    const int nb = (j + 1) * nv;  // basis vectors so far, all runs
+    void *Vj = (char *)w.LV + es * (size_t)N * j * nv;
+    gemv_block(cplx, H, ldh, (int)N, (int)N, Vj, N, nv, w.LW, N, w.SK, w.sk_bytes, c.stream);
+    dot_re_cols(cplx, Vj, w.LW, N, (int)N, nv, w.lz_ab + (size_t)j * nv, c.stream);
     for (int rep = 0; rep < 2; ++rep) {
       GemmArgs a = gargs();
       a.A = w.LV; a.lda = N;
       a.B = w.LW; a.ldb = N;
-      a.M = j + 1; a.N = 1; a.K = (int)N;
+      a.M = nb; a.N = nv; a.K = (int)N;
       a.k_per_split = (int)(((N + nsl - 1) / nsl + bk - 1) / bk * bk);
-      a.C = w.LhP; a.ldc = k; a.split_stride = k;
+      a.C = w.LhP; a.ldc = ldh_; a.split_stride = ldh_ * nv;
       gemm(cplx, false, true, false, false, GEMM_SMALL, a, nsl, c.stream);
-      sum_splits(cplx, w.LhP, nsl, k, j + 1, w.Lh, c.stream);
+      sum_splits_diag(cplx, w.LhP, nsl, ldh_ * nv, ldh_, nb, nv, w.Lh, ldh_, c.stream);
       GemmArgs b = gargs();
       b.A = w.LV; b.lda = N;
-      b.B = w.Lh; b.ldb = k;
-      b.M = (int)N; b.N = 1; b.K = j + 1;
+      b.B = w.Lh; b.ldb = ldh_;
+      b.M = (int)N; b.N = nv; b.K = nb;
       b.C = w.LW; b.ldc = N;
       b.alpha = -1.0; b.beta = 1.0;
       gemm(cplx, false, false, false, false, GEMM_BIG, b, 1, c.stream);
     }
-    norm_scale(cplx, w.LW, (int)N, (char *)w.LV + es * (size_t)N * (j + 1), w.lz_ab + k + j,
-               c.stream);
+    // beta_j of every run; v_{j+1} = w / beta_j
+    norm_scale_cols(cplx, w.LW, N, (int)N, nv, (char *)w.LV + es * (size_t)N * nb, N,
+                    w.lz_ab + (size_t)k * nv + (size_t)j * nv, c.stream);
   }
   CHASE_HIP(hipGetLastError());
-  CHASE_HIP(hipMemcpyAsync(w.h_ab, w.lz_ab, 16 * (size_t)k, hipMemcpyDeviceToHost, c.stream));
+  CHASE_HIP(hipMemcpyAsync(w.h_ab, w.lz_ab, 16 * (size_t)k * nv, hipMemcpyDeviceToHost,
+                           c.stream));
   CHASE_HIP(hipStreamSynchronize(c.stream));
-  alpha.assign(w.h_ab, w.h_ab + k);
-  beta.assign(w.h_ab + k, w.h_ab + 2 * k);
+  alpha.assign((size_t)k * nv, 0.0);
+  beta.assign((size_t)k * nv, 0.0);
+  for (int r = 0; r < nv; ++r)
+    for (int j = 0; j < k; ++j) {
+      alpha[(size_t)r * k + j] = w.h_ab[(size_t)j * nv + r];
+      beta[(size_t)r * k + j] = w.h_ab[(size_t)k * nv + (size_t)j * nv + r];
+    }
 }
 
 // -------------------------------------------------------------- the solve --
@@ -624,7 +650,8 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
   const int L = nev + nex;
   const size_t es = cplx ? 16 : 8;
   const int lz = o.have_bounds ? 0 : std::max(1, o.lanczos_steps);
-  c.ensure_work(N, L, cplx, mixed, lz);
+  const int lzv = std::max(1, o.lanczos_nvec);
+  c.ensure_work(N, L, cplx, mixed, lz, lzv);
   Work &w = c.w;
   hipStream_t s = c.stream;
   chase_info inf;
@@ -637,10 +664,10 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
   } else {
     CHASE_HIP(hipEventRecord(c.ev[6], s));
     std::vector<double> la, lb;
-    lanczos(c, cplx, H, ldh, N, o.lanczos_v0, lz, o.seed + 0x9E3779B97F4A7C15ull, la, lb);
+    lanczos(c, cplx, H, ldh, N, o.lanczos_v0, lzv, lz, o.seed + 0x9E3779B97F4A7C15ull, la, lb);
     CHASE_HIP(hipEventRecord(c.ev[7], s));
     double bd[3];
-    lanczos_bounds_from_tridiag(la, lb, N, L, bd);
+    lanczos_bounds_from_runs(la, lb, lzv, N, L, bd);
     gamma = bd[0]; alpha = bd[1]; beta = bd[2];
     CHASE_HIP(hipEventSynchronize(c.ev[7]));
     inf.t_lanczos = elapsed(c.ev[6], c.ev[7]);

@@ -14,7 +14,7 @@ struct Work {
   int64_t N = 0;
   int L = 0;
   bool cplx = false, mixed = false;
-  int nsplit = 1, lz_steps = 0, lz_split = 1;
+  int nsplit = 1, lz_steps = 0, lz_nvec = 1, lz_split = 1;
   char *base = nullptr;
   size_t bytes = 0;
   void *X0 = nullptr, *B1 = nullptr, *B2 = nullptr, *Xq = nullptr;  // N x L
@@ -24,7 +24,7 @@ struct Work {
   int *flag = nullptr, *deg = nullptr, *perm = nullptr, *rinfo = nullptr;
   void *tau = nullptr;
   void *H32 = nullptr;                                  // N x N in FP32 (mixed)
-  void *LV = nullptr, *LW = nullptr, *Lh = nullptr, *LhP = nullptr;  // Lanczos
+  void *LV = nullptr, *LW = nullptr, *Lh = nullptr, *LhP = nullptr;  // Lanczos runs
   double *lz_ab = nullptr;
   void *SK = nullptr;                                   // remainder-split partials
   size_t sk_bytes = 0;
@@ -33,7 +33,7 @@ struct Work {
   int *h_flag = nullptr, *h_ints = nullptr;
 };
 
-size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps);
+size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec);
 
 // Per-thread (or per-handle) execution context.
 struct Ctx {
@@ -46,7 +46,7 @@ struct Ctx {
   int h_cap_L = 0, h_cap_lz = 0;
   void ensure_init();
   void free_pinned();
-  void ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps);
+  void ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec = 1);
   void set_stream(hipStream_t s);
   void release();
 };
@@ -60,8 +60,10 @@ double log_cond_estimate(double theta_next, int m_next, int m_max, double lam1, 
 chase_qr select_qr(double est, double hi, double lo);
 void degrees(const double *theta, const double *resid, int n, double tol, double c, double e,
              int min_deg, int max_deg, int margin, int *out);
-void lanczos_bounds_from_tridiag(const std::vector<double> &alpha, const std::vector<double> &beta,
-                                 int64_t N, int nsearch, double bounds[3]);
+// Bounds from nvec Lanczos runs; alpha and beta hold run r's k coefficients
+// at [r * k, (r + 1) * k).
+void lanczos_bounds_from_runs(const std::vector<double> &alpha, const std::vector<double> &beta,
+                              int nvec, int64_t N, int nsearch, double bounds[3]);
 
 // Steps (device buffers; enqueue on ctx.stream).
 int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, void *bufs[3],
@@ -76,8 +78,8 @@ QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, c
          int inject);
 void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *Q,
                    int64_t ldq, int Lp, void *W, void *Vout, int64_t ldv, void *HV, int64_t ldhv);
-void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *v0, int steps,
-             uint64_t seed, std::vector<double> &alpha, std::vector<double> &beta);
+void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *V0, int nvec,
+             int steps, uint64_t seed, std::vector<double> &alpha, std::vector<double> &beta);
 
 chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_t ldh, int nev,
                    int nex, int degree, double tol, double *evals, void *evecs, int64_t ldv,

@@ -11,6 +11,7 @@ import pytest
 
 from oracle import degrees as odeg
 from oracle import estimate as oest
+from oracle import lanczos as olz
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "chase.h")
@@ -34,6 +35,7 @@ def test_header_declares_entry_points():
     names = declared_functions()
     for must in ["chase_solve", "chase_opts_default", "chase_filter", "chase_qr_factor",
                  "chase_rayleigh_ritz", "chase_residuals", "chase_lanczos",
+                 "chase_lanczos_bounds",
                  "chase_log_cond_estimate", "chase_select_qr", "chase_degrees",
                  "chase_handle_create", "chase_solve_async", "chase_handle_query",
                  "chase_handle_wait", "chase_handle_destroy", "chase_workspace_bytes",
@@ -77,6 +79,39 @@ def test_degree_rule_matches_oracle(pkg):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("family,nvec,nsearch", [("dft", 4, 30), ("stress", 4, 25), ("uniform", 1, 60),
+                                                 ("dft", 3, 200)])
+def test_lanczos_bounds_match_oracle(pkg, family, nvec, nsearch):
+    """The library's bounds logic (density count, top-pair residual, clamp)
+    on the oracle's Lanczos coefficients."""
+    import synth
+    N = 300
+    H, lam = synth.planted_numpy(N, family, 3, False, **({"n_low": 20} if family == "stress" else {}))
+    V0 = synth.lanczos_starts(N, nvec, 4)
+    runs = [olz.lanczos_tridiag(H, V0[:, r], 40) for r in range(nvec)]
+    ref = olz.bounds_from_runs(runs, N, nsearch)
+    got = pkg.chase_lanczos_bounds(np.array([a for a, _ in runs]), np.array([b for _, b in runs]),
+                                   N, nsearch)
+    scale = lam[-1] - lam[0]
+    assert np.allclose(got, ref, rtol=0, atol=1e-11 * scale)
+
+
+def test_lanczos_bounds_invariant_run(pkg):
+    """A run that reaches an invariant Krylov space (zero beta) ends there."""
+    N = 90
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    vals = np.array([-1.5] * 7 + [0.25] * 20 + [2.0] * (N - 27))
+    H = (Q * vals) @ Q.T
+    a, b = olz.lanczos_tridiag(H, rng.standard_normal(N), 3)
+    a6 = np.concatenate([a, np.zeros(3)])
+    b6 = np.concatenate([b[:2], [0.0], np.zeros(3)])  # the third step closes the space
+    ref = olz.bounds_from_runs([(a, np.concatenate([b[:2], [0.0]]))], N, 10)
+    got = pkg.chase_lanczos_bounds(a6, b6, N, 10)
+    assert np.allclose(got, ref, atol=1e-12)
+    assert got[0] == pytest.approx(-1.5, abs=1e-12) and got[2] == pytest.approx(2.0, abs=1e-12)
+
+
 def test_workspace_bytes(pkg):
     b1 = pkg.chase_workspace_bytes(1000, 40, 20)
     b2 = pkg.chase_workspace_bytes(1000, 40, 20, pkg.COMPLEX128)
@@ -108,3 +143,20 @@ def test_invalid_arguments_rejected_without_gpu(pkg):
                                  ev.ctypes.data_as(pkg._dp), ctypes.c_void_p(16), 10, None, None)
         assert st == pkg.CHASE_EINVAL, bad
     assert pkg.lib.chase_strerror(pkg.CHASE_EINVAL) == b"invalid argument"
+    for nv in (0, 9):
+        o = pkg.opts_default(lanczos_nvec=nv)
+        st = pkg.lib.chase_solve(ctypes.c_void_p(16), 10, 10, 2, 2, 20, 1e-10, ctypes.byref(o),
+                                 ev.ctypes.data_as(pkg._dp), ctypes.c_void_p(16), 10, None, None)
+        assert st == pkg.CHASE_EINVAL and b"lanczos_nvec" in pkg.lib.chase_last_error()
+    ab = np.zeros(40)
+    bd = np.zeros(3)
+    for nv, nsearch in ((0, 5), (9, 5), (1, 0), (1, 11)):
+        st = pkg.lib.chase_lanczos(pkg.REAL64, ctypes.c_void_p(16), 10, 10, ctypes.c_void_p(16), nv, 4,
+                                   nsearch,
+                                   ab.ctypes.data_as(pkg._dp), ab.ctypes.data_as(pkg._dp),
+                                   bd.ctypes.data_as(pkg._dp), None)
+        assert st == pkg.CHASE_EINVAL
+        if nv == 1:  # the host-only bounds take any nvec >= 1
+            st = pkg.lib.chase_lanczos_bounds(ab.ctypes.data_as(pkg._dp), ab.ctypes.data_as(pkg._dp),
+                                              nv, 4, 10, nsearch, bd.ctypes.data_as(pkg._dp))
+            assert st == pkg.CHASE_EINVAL

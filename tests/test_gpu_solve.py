@@ -104,11 +104,12 @@ def test_lanczos_bounds_path(P, gpu):
     N, nev, nex = 1000, 40, 20
     H, lam = synth.planted_numpy(N, "uniform", 1)
     V0 = synth.start_block(N, nev + nex, 11)
-    v0 = synth.lanczos_start(N, 12)
+    v0 = synth.lanczos_starts(N, 4, 12)  # the default four runs
     ref = osolver.chase_solve(H, nev, nex, 20, 1e-10, V0=V0, lanczos_v0=v0)
     v0d = to_dev(v0, gpu)
     out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=to_dev(V0, gpu), warm_start=1,
                         lanczos_v0=v0d.data_ptr())
+    assert ref.bounds[2] >= lam[-1]
     assert out["status"] == P.CHASE_OK
     assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10
     assert out["info"]["lambda_max"] == pytest.approx(ref.bounds[2], rel=1e-9)

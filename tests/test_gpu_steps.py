@@ -153,20 +153,48 @@ def test_rayleigh_ritz_and_residuals(P, gpu, N, L, cplx):
     assert np.max(np.abs(r2 - r_ref)) <= 1e-10 * scale
 
 
-@pytest.mark.parametrize("N,cplx", [(1000, False), (700, True)])
-def test_lanczos_matches_oracle(P, gpu, N, cplx):
+@pytest.mark.parametrize("N,cplx,nvec", [(1000, False, 1), (700, True, 1), (1000, False, 4),
+                                         (1537, True, 4), (333, False, 3), (2100, True, 8)])
+def test_lanczos_matches_oracle(P, gpu, N, cplx, nvec):
+    """nvec runs advanced as one block (the N x N product streams H once for
+    all of them) against the oracle's runs one by one; sizes span one and
+    several row blocks and column splits of the product, with ragged ends."""
+    print("lanczos case", N, cplx, nvec, flush=True)
     H, lam = synth.planted_numpy(N, "dft", 15, cplx)
-    v0 = synth.lanczos_start(N, 16, cplx)
-    a_ref, b_ref = olanczos.lanczos_tridiag(H, v0, 40)
-    bounds_ref = olanczos.lanczos_bounds(H, 60, v0, 40)
-    a, b, bounds = P.chase_lanczos(to_dev(H, gpu), to_dev(v0, gpu), 40, 60)
+    V0 = synth.lanczos_starts(N, nvec, 16, cplx)
+    runs = [olanczos.lanczos_tridiag(H, V0[:, r], 40) for r in range(nvec)]
+    bounds_ref = olanczos.lanczos_bounds(H, 60, V0, 40)
+    a, b, bounds = P.chase_lanczos(to_dev(H, gpu), to_dev(V0, gpu), 40, 60)
     scale = np.max(np.abs(lam))
-    # Lanczos with full reorthogonalisation is forward stable here; the
-    # coefficients drift by a few ulps per step
-    assert np.max(np.abs(a - a_ref)) <= 1e-9 * scale
-    assert np.max(np.abs(b - b_ref)) <= 1e-9 * scale
+    assert a.shape == (nvec, 40) and b.shape == (nvec, 40)
+    for r, (a_ref, b_ref) in enumerate(runs):
+        # Lanczos with full reorthogonalisation is forward stable here; the
+        # coefficients drift by a few ulps per step
+        assert np.max(np.abs(a[r] - a_ref)) <= 1e-9 * scale, r
+        assert np.max(np.abs(b[r] - b_ref)) <= 1e-9 * scale, r
     assert np.allclose(bounds, bounds_ref, rtol=1e-8, atol=1e-9 * scale)
     assert bounds[2] >= lam[-1]
+
+
+@pytest.mark.parametrize("N,cplx", [(20000, True), (10000, False)])
+def test_lanczos_first_step_full_size(P, gpu, N, cplx):
+    """At full size: the first coefficients of each run against torch's own
+    matrix product, alpha_0 = v^H H v and beta_0 = ||H v - alpha_0 v|| for
+    the normalised start vector v, and the upper-bound property."""
+    import torch
+    print("lanczos full-size case", N, cplx, flush=True)
+    Hd, lam = synth.planted_torch(N, "dft", 41, cplx, gpu)
+    V0 = synth.start_block_torch(N, 4, 42, cplx, gpu)
+    a, b, bounds = P.chase_lanczos(Hd, V0, 3, int(0.065 * N))
+    torch.cuda.synchronize()
+    v = V0 / torch.linalg.vector_norm(V0, dim=0, keepdim=True)
+    Hv = Hd @ v
+    a0 = torch.real(torch.sum(v.conj() * Hv, dim=0))
+    b0 = torch.linalg.vector_norm(Hv - v * a0, dim=0)
+    scale = float(np.max(np.abs(lam)))
+    assert np.max(np.abs(a[:, 0] - a0.cpu().numpy())) <= 1e-12 * scale
+    assert np.max(np.abs(b[:, 0] - b0.cpu().numpy())) <= 1e-12 * scale
+    assert bounds[0] >= lam[0] - 1e-9 * scale
 
 
 @pytest.mark.parametrize("N,ncols,cplx,maxdeg", [(3000, 1300, True, 6), (2500, 700, False, 5),
