@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <numeric>
 
 #include "gemm.hpp"
@@ -55,59 +56,65 @@ void degrees(const double *theta, const double *resid, int n, double tol, double
   }
 }
 
-// Cyclic Jacobi eigen-decomposition of a small dense symmetric matrix
-// (row-major n x n); returns ascending eigenvalues and the matching
-// eigenvectors as columns of V (row-major).
-static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w,
-                       std::vector<double> &V) {
-  V.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        const double v = A[(size_t)i * n + j] * A[(size_t)i * n + j];
-        tot += v;
-        if (i != j) off += v;
+// Eigenvalues of the symmetric tridiagonal T (diagonal d[0..n), off-diagonal
+// e[0..n-1)) by implicit QR steps with the Wilkinson shift (Golub & Van Loan,
+// Matrix Computations, Sec. 8.3), in band storage: each step chases a bulge
+// down the active block with Givens rotations.  Only rows 0 and n-1 of the
+// eigenvector matrix are accumulated (first[j], last[j]: first and last
+// component of the unit eigenvector of w[j]); O(n) work per step.  Output in
+// ascending order of w.
+static void tridiag_eig(int n, std::vector<double> d, std::vector<double> e,
+                        std::vector<double> &w, std::vector<double> &first,
+                        std::vector<double> &last) {
+  std::vector<double> z0(n, 0.0), z1(n, 0.0);  // rows 0 and n-1 of Q
+  z0[0] = 1.0;
+  z1[n - 1] = 1.0;
+  e.resize(std::max(n - 1, 0));
+  const double eps = std::numeric_limits<double>::epsilon();
+  const int max_steps = 30 * std::max(n, 1);
+  for (int step = 0; step < max_steps; ++step) {
+    for (int i = 0; i + 1 < n; ++i)
+      if (std::fabs(e[i]) <= eps * (std::fabs(d[i]) + std::fabs(d[i + 1]))) e[i] = 0.0;
+    int m = n - 1;
+    while (m > 0 && e[m - 1] == 0.0) --m;
+    if (m == 0) break;
+    int l = m - 1;
+    while (l > 0 && e[l - 1] != 0.0) --l;
+    // Wilkinson shift: the eigenvalue of the trailing 2 x 2 nearer d[m]
+    const double del = 0.5 * (d[m - 1] - d[m]);
+    const double em = e[m - 1];
+    const double mu = d[m] - em * em / (del + (del >= 0.0 ? 1.0 : -1.0) * std::hypot(del, em));
+    double x = d[l] - mu, zb = e[l];
+    for (int k = l; k < m; ++k) {
+      // rotation G = [c s; -s c] with G^T (x, zb)^T = (r, 0)^T
+      const double r = std::hypot(x, zb);
+      const double c = r > 0.0 ? x / r : 1.0, sn = r > 0.0 ? -zb / r : 0.0;
+      if (k > l) e[k - 1] = r;  // row k-1 loses its bulge
+      const double p = d[k], q = e[k], t = d[k + 1];
+      d[k] = c * c * p - 2.0 * c * sn * q + sn * sn * t;
+      d[k + 1] = sn * sn * p + 2.0 * c * sn * q + c * c * t;
+      e[k] = c * sn * (p - t) + (c * c - sn * sn) * q;
+      if (k + 1 < m) {  // new bulge at (k, k + 2)
+        zb = -sn * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+        x = e[k];
       }
-    if (off <= 1e-32 * tot || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[(size_t)p * n + q];
-        if (apq == 0.0) continue;
-        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-        const double th = (aqq - app) / (2.0 * apq);
-        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        for (int k = 0; k < n; ++k) {  // columns p, q
-          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-          A[(size_t)k * n + p] = cs * akp - sn * akq;
-          A[(size_t)k * n + q] = sn * akp + cs * akq;
-        }
-        for (int k = 0; k < n; ++k) {  // rows p, q
-          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-          A[(size_t)p * n + k] = cs * apk - sn * aqk;
-          A[(size_t)q * n + k] = sn * apk + cs * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
-          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
-        }
-      }
+      const double a0 = z0[k], b0 = z0[k + 1], a1 = z1[k], b1 = z1[k + 1];
+      z0[k] = c * a0 - sn * b0; z0[k + 1] = sn * a0 + c * b0;
+      z1[k] = c * a1 - sn * b1; z1[k + 1] = sn * a1 + c * b1;
+    }
   }
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-    return A[(size_t)a * n + a] < A[(size_t)b * n + b];
-  });
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
   w.resize(n);
-  std::vector<double> Vs((size_t)n * n);
+  first.resize(n);
+  last.resize(n);
   for (int j = 0; j < n; ++j) {
-    w[j] = A[(size_t)idx[j] * n + idx[j]];
-    for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + idx[j]];
+    w[j] = d[idx[j]];
+    first[j] = z0[idx[j]];
+    last[j] = z1[idx[j]];
   }
-  V.swap(Vs);
 }
 
 // Bounds from nvec Lanczos runs (Sec. 1.2 needs only the upper end to bound
@@ -129,19 +136,13 @@ void lanczos_bounds_from_runs(const std::vector<double> &alpha, const std::vecto
     int k = kmax;
     for (int j = 0; j < kmax; ++j)
       if (b[j] == 0.0) { k = j + 1; break; }
-    std::vector<double> T((size_t)k * k, 0.0), w, V;
-    for (int j = 0; j < k; ++j) {
-      T[(size_t)j * k + j] = a[j];
-      if (j + 1 < k) {
-        T[(size_t)j * k + j + 1] = b[j];
-        T[(size_t)(j + 1) * k + j] = b[j];
-      }
-    }
-    jacobi_eig(k, T, w, V);  // V[i * k + j]: component i of eigenvector j
-    const double top_resid = std::fabs(b[k - 1]) * std::fabs(V[(size_t)(k - 1) * k + (k - 1)]);
+    std::vector<double> w, first, last;
+    tridiag_eig(k, std::vector<double>(a, a + k), std::vector<double>(b, b + k - 1), w, first,
+                last);
+    const double top_resid = std::fabs(b[k - 1]) * std::fabs(last[k - 1]);
     up = std::max(up, w[k - 1] + 2.0 * top_resid);
     low = std::min(low, w[0]);
-    for (int j = 0; j < k; ++j) dos.push_back({w[j], (double)N * V[j] * V[j] / nvec});
+    for (int j = 0; j < k; ++j) dos.push_back({w[j], (double)N * first[j] * first[j] / nvec});
   }
   std::stable_sort(dos.begin(), dos.end(),
                    [](const std::pair<double, double> &x, const std::pair<double, double> &y) {

@@ -79,16 +79,19 @@ def test_degree_rule_matches_oracle(pkg):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("family,nvec,nsearch", [("dft", 4, 30), ("stress", 4, 25), ("uniform", 1, 60),
-                                                 ("dft", 3, 200)])
-def test_lanczos_bounds_match_oracle(pkg, family, nvec, nsearch):
-    """The library's bounds logic (density count, top-pair residual, clamp)
-    on the oracle's Lanczos coefficients."""
+@pytest.mark.parametrize("family,nvec,nsearch,steps", [("dft", 4, 30, 40), ("stress", 4, 25, 40),
+                                                       ("uniform", 1, 60, 40), ("dft", 3, 200, 40),
+                                                       ("uniform", 2, 60, 150), ("dft", 1, 5, 1)])
+def test_lanczos_bounds_match_oracle(pkg, family, nvec, nsearch, steps):
+    """The library's bounds logic (its tridiagonal eigensolver, density
+    count, top-pair residual, clamp) on the oracle's Lanczos coefficients;
+    150 steps on N = 300 leave many converged Ritz values (tiny
+    off-diagonals: the deflation path)."""
     import synth
     N = 300
     H, lam = synth.planted_numpy(N, family, 3, False, **({"n_low": 20} if family == "stress" else {}))
     V0 = synth.lanczos_starts(N, nvec, 4)
-    runs = [olz.lanczos_tridiag(H, V0[:, r], 40) for r in range(nvec)]
+    runs = [olz.lanczos_tridiag(H, V0[:, r], steps) for r in range(nvec)]
     ref = olz.bounds_from_runs(runs, N, nsearch)
     got = pkg.chase_lanczos_bounds(np.array([a for a, _ in runs]), np.array([b for _, b in runs]),
                                    N, nsearch)
