@@ -157,6 +157,142 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &p, int i, int j, 
   }
 }
 
+// ---------------------------------------------------- direct-load path --
+// Complex FP64 tiles of 64 x 64 with K chunks of 8, both operands
+// K-contiguous (the filter's H^H and X): a ring of three LDS stages fed by
+// direct global -> LDS loads (global_load_lds_dwordx4: lane L of a wave
+// writes its 16 bytes to the L-th slot after the wave's LDS base), so two
+// chunks are in flight while a third is multiplied, with no prefetch
+// registers and no LDS store instructions.
+#ifndef CHASE_GEMM_DMA
+#define CHASE_GEMM_DMA 1
+#endif
+typedef double __attribute__((ext_vector_type(2))) dbl2;
+typedef dbl2 __attribute__((address_space(3))) LdsD2;
+
+// LDS slot of element (row r, k) of a 64 x 8 complex tile: rows of eight
+// 16-byte elements, k XOR-swizzled with bits 1..3 of the row so that the 16
+// rows one quarter-wave reads for a fixed k hit 16 different groups of four
+// banks.
+__device__ __forceinline__ int dma_slot(int r, int k) { return 8 * r + (k ^ ((r >> 1) & 7)); }
+
+// One full K chunk [k0, k0 + 8) of A (rows m0..m0+63) and B (columns
+// n0..n0+63) into the tiles LA, LB: each wave issues two 1 KB loads per tile,
+// lane L of load q filling slot 64 q + L.  Rows (columns) past the matrix read
+// the last one instead: they only feed outputs that are not stored.
+__device__ __forceinline__ void dma_chunk(const GemmArgs &p, int m0, int n0, int k0, int wave,
+                                          int lane, LdsD2 *LA, LdsD2 *LB) {
+  typedef const dbl2 __attribute__((address_space(1))) G2;
+  const G2 *Ag = (const G2 *)p.A;
+  const G2 *Bg = (const G2 *)p.B;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = 2 * wave + h;
+    const int s = 64 * q + lane;
+    const int r = s >> 3;
+    const int k = (s & 7) ^ ((r >> 1) & 7);
+    const int gi = min(m0 + r, p.M - 1);
+    const int gj = min(n0 + r, p.N - 1);
+    __builtin_amdgcn_global_load_lds(Ag + (int64_t)gi * p.lda + (k0 + k), LA + 64 * q, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(Bg + (int64_t)(p.col0 + gj) * p.ldb + (k0 + k), LB + 64 * q,
+                                     16, 0, 0);
+  }
+}
+
+// The partial last chunk [k0, kend): ordinary loads with zero fill (k past
+// kend must contribute nothing), stored in the same layout.
+__device__ __forceinline__ void reg_chunk(const GemmArgs &p, int m0, int n0, int k0, int kend,
+                                          int tid, LdsD2 *LA, LdsD2 *LB) {
+  typedef const dbl2 __attribute__((address_space(1))) G2;
+  const G2 *Ag = (const G2 *)p.A;
+  const G2 *Bg = (const G2 *)p.B;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int s = tid + 256 * t;
+    const int r = s >> 3;
+    const int k = (s & 7) ^ ((r >> 1) & 7);
+    const bool kin = k0 + k < kend;
+    const dbl2 z = {0.0, 0.0};
+    LA[s] = (kin && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + (k0 + k)] : z;
+    LB[s] = (kin && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + (k0 + k)] : z;
+  }
+}
+
+// The K loop of the direct-load path.  The six stage tiles are restrict
+// parameters of one inlined function, so the compiler knows that reading
+// stage c % 3 does not depend on the loads just issued into the other stages
+// and waits only for the loads of chunk c; the explicit wait before the
+// barrier makes every wave's loads of chunk c visible to the others.
+template <bool CONJA>
+__device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
+                                             int tid, int wm, int wn, d4v (&accR)[2][2],
+                                             d4v (&accI)[2][2], d4v (&acc3)[2][2],
+                                             LdsD2 *__restrict__ A0, LdsD2 *__restrict__ B0,
+                                             LdsD2 *__restrict__ A1, LdsD2 *__restrict__ B1,
+                                             LdsD2 *__restrict__ A2, LdsD2 *__restrict__ B2) {
+  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nch = kend > kbeg ? (kend - kbeg + 7) / 8 : 0;
+  auto full = [&](int c) { return kbeg + 8 * c + 8 <= kend; };
+  auto issue = [&](int c, LdsD2 *LA, LdsD2 *LB) {
+    const int k0 = kbeg + 8 * c;
+    if (full(c))
+      dma_chunk(p, m0, n0, k0, wave_u, lane, LA, LB);
+    else
+      reg_chunk(p, m0, n0, k0, kend, tid, LA, LB);
+  };
+  auto compute = [&](const LdsD2 *LA, const LdsD2 *LB) {
+#pragma unroll
+    for (int kk = 0; kk < 8; kk += 4) {
+      double ar[2], ai[2], as_[2], br[2], bi[2], bs_[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const dbl2 v = LA[dma_slot(wm * 32 + a * 16 + lr, kk + lk)];
+        ar[a] = v.x;
+        ai[a] = v.y;
+        as_[a] = CONJA ? v.x - v.y : v.x + v.y;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const dbl2 v = LB[dma_slot(wn * 32 + b * 16 + lr, kk + lk)];
+        br[b] = v.x;
+        bi[b] = v.y;
+        bs_[b] = v.x + v.y;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accR[a][b] = Mfma<double>::op(ar[a], br[b], accR[a][b]);
+          accI[a][b] = Mfma<double>::op(ai[a], bi[b], accI[a][b]);
+          acc3[a][b] = Mfma<double>::op(as_[a], bs_[b], acc3[a][b]);
+        }
+    }
+  };
+  // chunk c: wait for its loads (the next chunk's four, if direct, may stay
+  // in flight), barrier (chunk c visible; every wave is done with chunk
+  // c - 1, whose stage the load of chunk c + 2 reuses), multiply.
+  auto step = [&](int c, const LdsD2 *Ac, const LdsD2 *Bc, LdsD2 *An, LdsD2 *Bn) {
+    if (c + 1 < nch && full(c + 1))
+      __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4)
+    else
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // LDS barrier without the memory fence of __syncthreads, whose implied
+    // vmcnt(0) would also drain the next chunk's loads; the clobber keeps
+    // the compiler from moving memory accesses across it
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (c + 2 < nch) issue(c + 2, An, Bn);
+    compute(Ac, Bc);
+  };
+  if (nch > 0) issue(0, A0, B0);
+  if (nch > 1) issue(1, A1, B1);
+  for (int c = 0; c < nch; c += 3) {
+    step(c, A0, B0, A2, B2);
+    if (c + 1 < nch) step(c + 1, A1, B1, A0, B0);
+    if (c + 2 < nch) step(c + 2, A2, B2, A1, B1);
+  }
+}
+
 // M3 (complex only): three real products per complex one,
 // P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2,
 // im = P3 - P1 - P2 (a quarter fewer MFMAs than the four-product form).
@@ -172,9 +308,8 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
   constexpr int NP = CPLX ? 2 : 1;
   constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
   static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile / thread mismatch");
-
-  __shared__ T As[2][NP][BK][BM + 1];
-  __shared__ T Bs[2][NP][BK][BN + 1];
+  constexpr bool DMA = CHASE_GEMM_DMA && M3 && AT && sizeof(T) == 8 && BM == 64 && BN == 64 &&
+                       BK == 8 && WM == 32 && WN == 32;
 
   if (p.flag != nullptr && *p.flag != 0) return;
 
@@ -221,9 +356,17 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
         if constexpr (M3) acc3[a][b][r] = 0;
       }
 
+  const int lr = lane & 15, lk = lane >> 4;
+  if constexpr (DMA) {
+    __shared__ dbl2 L0[2][512], L1[2][512], L2[2][512];
+    dma_mainloop<CONJA>(p, m0, n0, kbeg, kend, tid, wm, wn, accR, accI, acc3,
+                        (LdsD2 *)L0[0], (LdsD2 *)L0[1], (LdsD2 *)L1[0], (LdsD2 *)L1[1],
+                        (LdsD2 *)L2[0], (LdsD2 *)L2[1]);
+  } else {
+  __shared__ T As[2][NP][BK][BM + 1];
+  __shared__ T Bs[2][NP][BK][BN + 1];
   E ra[AE], rb[BE];
   const E zero = mmake<E, T>((T)0, (T)0);
-
   auto load_tiles = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < AE; ++e) {
@@ -265,7 +408,6 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
     }
   };
 
-  const int lr = lane & 15, lk = lane >> 4;
   int buf = 0;
   if (kbeg < kend) {
     load_tiles(kbeg);
@@ -322,6 +464,8 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
     buf ^= 1;
   }
 
+  }
+
   // ---------------------------------------------------------- epilogue --
   if constexpr (M3) {  // (P1, P2, P3) -> (re, im)
 #pragma unroll
@@ -330,7 +474,11 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const T p1 = accR[a][b][r], p2 = accI[a][b][r];
+          // the direct-load path multiplies the stored (unconjugated)
+          // imaginary part of A: with CONJA, P2 = -ai bi and
+          // P3 = (ar + ai)(br + bi) with ai the conjugate's part
+          const T p1 = accR[a][b][r];
+          const T p2 = (DMA && CONJA) ? -accI[a][b][r] : accI[a][b][r];
           accR[a][b][r] = p1 - p2;
           accI[a][b][r] = acc3[a][b][r] - p1 - p2;
         }
