@@ -158,63 +158,82 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &p, int i, int j, 
 }
 
 // ---------------------------------------------------- direct-load path --
-// Complex FP64 tiles of 64 x 64 with K chunks of 8, both operands
-// K-contiguous (the filter's H^H and X): a ring of three LDS stages fed by
-// direct global -> LDS loads (global_load_lds_dwordx4: lane L of a wave
-// writes its 16 bytes to the L-th slot after the wave's LDS base), so two
+// Complex tiles of 64 x 64 with both operands K-contiguous (the filter's H^H
+// and X, and the Rayleigh-Ritz product H Q): a ring of three LDS stages fed
+// by direct global -> LDS loads (global_load_lds_dwordx4: lane L of a wave
+// writes its 16 bytes to the L-th slot after the wave's LDS base), so two K
 // chunks are in flight while a third is multiplied, with no prefetch
-// registers and no LDS store instructions.
+// registers and no LDS store instructions.  A K chunk is 128 bytes of every
+// row: 8 complex doubles or 16 complex floats, i.e. eight 16-byte slots of
+// one (double) or two (float) elements.
 #ifndef CHASE_GEMM_DMA
 #define CHASE_GEMM_DMA 1
 #endif
 typedef double __attribute__((ext_vector_type(2))) dbl2;
-typedef dbl2 __attribute__((address_space(3))) LdsD2;
+typedef float __attribute__((ext_vector_type(4))) flt4;
+typedef dbl2 __attribute__((address_space(3))) LdsD2;  // one 16-byte slot
+typedef flt4 __attribute__((address_space(3))) LdsF4;
 
-// LDS slot of element (row r, k) of a 64 x 8 complex tile: rows of eight
-// 16-byte elements, k XOR-swizzled with bits 1..3 of the row so that the 16
-// rows one quarter-wave reads for a fixed k hit 16 different groups of four
-// banks.
-__device__ __forceinline__ int dma_slot(int r, int k) { return 8 * r + (k ^ ((r >> 1) & 7)); }
+// LDS slot of (row r, slot column c) of a 64-row tile: rows of eight slots,
+// c XOR-swizzled with bits 1..3 of the row so that the 16 rows one
+// quarter-wave reads for a fixed c hit 16 different groups of four banks.
+__device__ __forceinline__ int dma_slot(int r, int c) { return 8 * r + (c ^ ((r >> 1) & 7)); }
 
-// One full K chunk [k0, k0 + 8) of A (rows m0..m0+63) and B (columns
+// One full K chunk [k0, k0 + 8 EPS) of A (rows m0..m0+63) and B (columns
 // n0..n0+63) into the tiles LA, LB: each wave issues two 1 KB loads per tile,
 // lane L of load q filling slot 64 q + L.  Rows (columns) past the matrix read
-// the last one instead: they only feed outputs that are not stored.
+// the last one instead: they only feed outputs that are not stored.  ES is
+// the element size in bytes, EPS = 16 / ES elements per slot.
+template <int ES>
 __device__ __forceinline__ void dma_chunk(const GemmArgs &p, int m0, int n0, int k0, int wave,
                                           int lane, LdsD2 *LA, LdsD2 *LB) {
-  typedef const dbl2 __attribute__((address_space(1))) G2;
-  const G2 *Ag = (const G2 *)p.A;
-  const G2 *Bg = (const G2 *)p.B;
+  constexpr int EPS = 16 / ES;
+  typedef const char __attribute__((address_space(1))) GC;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int q = 2 * wave + h;
     const int s = 64 * q + lane;
     const int r = s >> 3;
-    const int k = (s & 7) ^ ((r >> 1) & 7);
+    const int c = (s & 7) ^ ((r >> 1) & 7);
     const int gi = min(m0 + r, p.M - 1);
     const int gj = min(n0 + r, p.N - 1);
-    __builtin_amdgcn_global_load_lds(Ag + (int64_t)gi * p.lda + (k0 + k), LA + 64 * q, 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(Bg + (int64_t)(p.col0 + gj) * p.ldb + (k0 + k), LB + 64 * q,
-                                     16, 0, 0);
+    const GC *a = (const GC *)p.A + ((int64_t)gi * p.lda + k0 + c * EPS) * ES;
+    const GC *b = (const GC *)p.B + ((int64_t)(p.col0 + gj) * p.ldb + k0 + c * EPS) * ES;
+    __builtin_amdgcn_global_load_lds(a, LA + 64 * q, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(b, LB + 64 * q, 16, 0, 0);
   }
 }
 
 // The partial last chunk [k0, kend): ordinary loads with zero fill (k past
 // kend must contribute nothing), stored in the same layout.
+template <typename T>
 __device__ __forceinline__ void reg_chunk(const GemmArgs &p, int m0, int n0, int k0, int kend,
                                           int tid, LdsD2 *LA, LdsD2 *LB) {
-  typedef const dbl2 __attribute__((address_space(1))) G2;
-  const G2 *Ag = (const G2 *)p.A;
-  const G2 *Bg = (const G2 *)p.B;
+  typedef T __attribute__((ext_vector_type(2))) E;
+  typedef const E __attribute__((address_space(1))) GE;
+  constexpr int EPS = 16 / (int)sizeof(E);
+  const GE *Ag = (const GE *)p.A;
+  const GE *Bg = (const GE *)p.B;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int s = tid + 256 * t;
     const int r = s >> 3;
-    const int k = (s & 7) ^ ((r >> 1) & 7);
-    const bool kin = k0 + k < kend;
-    const dbl2 z = {0.0, 0.0};
-    LA[s] = (kin && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + (k0 + k)] : z;
-    LB[s] = (kin && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + (k0 + k)] : z;
+    const int c = (s & 7) ^ ((r >> 1) & 7);
+    E va[EPS], vb[EPS];
+#pragma unroll
+    for (int e = 0; e < EPS; ++e) {
+      const int k = k0 + c * EPS + e;
+      const E z = {(T)0, (T)0};
+      va[e] = (k < kend && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + k] : z;
+      vb[e] = (k < kend && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + k] : z;
+    }
+    if constexpr (EPS == 1) {
+      LA[s] = va[0];
+      LB[s] = vb[0];
+    } else {
+      ((LdsF4 *)LA)[s] = (flt4){va[0].x, va[0].y, va[1].x, va[1].y};
+      ((LdsF4 *)LB)[s] = (flt4){vb[0].x, vb[0].y, vb[1].x, vb[1].y};
+    }
   }
 }
 
@@ -223,50 +242,81 @@ __device__ __forceinline__ void reg_chunk(const GemmArgs &p, int m0, int n0, int
 // stage c % 3 does not depend on the loads just issued into the other stages
 // and waits only for the loads of chunk c; the explicit wait before the
 // barrier makes every wave's loads of chunk c visible to the others.
-template <bool CONJA>
+// K order inside a chunk: MFMA step t, lane group lk multiplies the element
+// in slot column lk + 4 (t / EPS) (element t % EPS of the slot), the same
+// for A and B, so every k of the chunk is used once.
+template <typename T, bool CONJA>
 __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
-                                             int tid, int wm, int wn, d4v (&accR)[2][2],
-                                             d4v (&accI)[2][2], d4v (&acc3)[2][2],
+                                             int tid, int wm, int wn,
+                                             typename Mfma<T>::acc (&accR)[2][2],
+                                             typename Mfma<T>::acc (&accI)[2][2],
+                                             typename Mfma<T>::acc (&acc3)[2][2],
                                              LdsD2 *__restrict__ A0, LdsD2 *__restrict__ B0,
                                              LdsD2 *__restrict__ A1, LdsD2 *__restrict__ B1,
                                              LdsD2 *__restrict__ A2, LdsD2 *__restrict__ B2) {
+  constexpr int ES = 2 * (int)sizeof(T), EPS = 16 / ES, BK = 8 * EPS;
   const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int nch = kend > kbeg ? (kend - kbeg + 7) / 8 : 0;
-  auto full = [&](int c) { return kbeg + 8 * c + 8 <= kend; };
+  const int nch = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  auto full = [&](int c) { return kbeg + BK * c + BK <= kend; };
   auto issue = [&](int c, LdsD2 *LA, LdsD2 *LB) {
-    const int k0 = kbeg + 8 * c;
+    const int k0 = kbeg + BK * c;
     if (full(c))
-      dma_chunk(p, m0, n0, k0, wave_u, lane, LA, LB);
+      dma_chunk<ES>(p, m0, n0, k0, wave_u, lane, LA, LB);
     else
-      reg_chunk(p, m0, n0, k0, kend, tid, LA, LB);
+      reg_chunk<T>(p, m0, n0, k0, kend, tid, LA, LB);
+  };
+  auto mma = [&](const T (&ar)[2], const T (&ai)[2], const T (&br)[2], const T (&bi)[2]) {
+    T as_[2], bs_[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) as_[a] = CONJA ? ar[a] - ai[a] : ar[a] + ai[a];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bs_[b] = br[b] + bi[b];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        accR[a][b] = Mfma<T>::op(ar[a], br[b], accR[a][b]);
+        accI[a][b] = Mfma<T>::op(ai[a], bi[b], accI[a][b]);
+        acc3[a][b] = Mfma<T>::op(as_[a], bs_[b], acc3[a][b]);
+      }
   };
   auto compute = [&](const LdsD2 *LA, const LdsD2 *LB) {
 #pragma unroll
-    for (int kk = 0; kk < 8; kk += 4) {
-      double ar[2], ai[2], as_[2], br[2], bi[2], bs_[2];
+    for (int g = 0; g < 2; ++g) {  // slot columns lk and lk + 4
+      const int c = lk + 4 * g;
+      if constexpr (EPS == 1) {
+        T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const dbl2 v = LA[dma_slot(wm * 32 + a * 16 + lr, kk + lk)];
-        ar[a] = v.x;
-        ai[a] = v.y;
-        as_[a] = CONJA ? v.x - v.y : v.x + v.y;
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const dbl2 v = LB[dma_slot(wn * 32 + b * 16 + lr, kk + lk)];
-        br[b] = v.x;
-        bi[b] = v.y;
-        bs_[b] = v.x + v.y;
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a) {
+          const dbl2 v = LA[dma_slot(wm * 32 + a * 16 + lr, c)];
+          ar[a] = v.x;
+          ai[a] = v.y;
+        }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          accR[a][b] = Mfma<double>::op(ar[a], br[b], accR[a][b]);
-          accI[a][b] = Mfma<double>::op(ai[a], bi[b], accI[a][b]);
-          acc3[a][b] = Mfma<double>::op(as_[a], bs_[b], acc3[a][b]);
+          const dbl2 v = LB[dma_slot(wn * 32 + b * 16 + lr, c)];
+          br[b] = v.x;
+          bi[b] = v.y;
         }
+        mma(ar, ai, br, bi);
+      } else {
+        flt4 va[2], vb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) va[a] = ((const LdsF4 *)LA)[dma_slot(wm * 32 + a * 16 + lr, c)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) vb[b] = ((const LdsF4 *)LB)[dma_slot(wn * 32 + b * 16 + lr, c)];
+        {
+          const T ar[2] = {va[0].x, va[1].x}, ai[2] = {va[0].y, va[1].y};
+          const T br[2] = {vb[0].x, vb[1].x}, bi[2] = {vb[0].y, vb[1].y};
+          mma(ar, ai, br, bi);
+        }
+        {
+          const T ar[2] = {va[0].z, va[1].z}, ai[2] = {va[0].w, va[1].w};
+          const T br[2] = {vb[0].z, vb[1].z}, bi[2] = {vb[0].w, vb[1].w};
+          mma(ar, ai, br, bi);
+        }
+      }
     }
   };
   // chunk c: wait for its loads (the next chunk's four, if direct, may stay
@@ -297,7 +347,7 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
 // P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2,
 // im = P3 - P1 - P2 (a quarter fewer MFMAs than the four-product form).
 template <typename T, bool CPLX, bool AT, bool CONJA, int BM, int BN, int BK, int WM, int WN,
-          int EPI, typename FT, int MINB, bool M3>
+          int EPI, typename FT, int MINB, bool M3, bool DMAP>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(const GemmArgs p) {
   typedef typename MemT<T, CPLX>::type E;
   typedef typename Mfma<T>::acc Acc;
@@ -308,8 +358,10 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
   constexpr int NP = CPLX ? 2 : 1;
   constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
   static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile / thread mismatch");
-  constexpr bool DMA = CHASE_GEMM_DMA && M3 && AT && sizeof(T) == 8 && BM == 64 && BN == 64 &&
-                       BK == 8 && WM == 32 && WN == 32;
+  // direct-load path (the launcher checks 16-byte alignment of the operands)
+  constexpr bool DMA = DMAP && M3 && AT && BM == 64 && BN == 64 && WM == 32 && WN == 32 &&
+                       BK == 128 / (2 * (int)sizeof(T));
+  static_assert(!DMAP || DMA, "direct-load path needs 64 x 64 complex tiles, K chunks of 128 bytes");
 
   if (p.flag != nullptr && *p.flag != 0) return;
 
@@ -359,7 +411,7 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
   const int lr = lane & 15, lk = lane >> 4;
   if constexpr (DMA) {
     __shared__ dbl2 L0[2][512], L1[2][512], L2[2][512];
-    dma_mainloop<CONJA>(p, m0, n0, kbeg, kend, tid, wm, wn, accR, accI, acc3,
+    dma_mainloop<T, CONJA>(p, m0, n0, kbeg, kend, tid, wm, wn, accR, accI, acc3,
                         (LdsD2 *)L0[0], (LdsD2 *)L0[1], (LdsD2 *)L1[0], (LdsD2 *)L1[1],
                         (LdsD2 *)L2[0], (LdsD2 *)L2[1]);
   } else {

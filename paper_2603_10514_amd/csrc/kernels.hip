@@ -580,6 +580,51 @@ template <typename K> static int resident_blocks(K kernel, int nthreads) {
   return ncu * per;
 }
 
+// Launch of one GEMM kernel over the tiles of C, with the remainder split:
+// the tiles beyond the last full wave of resident blocks are split along K
+// across the idle slots of that wave; their partial sums go to the scratch
+// and a reduce kernel applies the epilogue.
+template <auto KERNEL, typename T, bool CPLX, int EPI, typename FT, int SHAPE, int BM, int BN,
+          int NT>
+static int launch_tiles(GemmArgs &a, int splits, hipStream_t s) {
+  const int nbm = (a.M + BM - 1) / BM, nbn = (a.N + BN - 1) / BN;
+  if (nbm <= 0 || nbn <= 0) return 0;
+  if (splits < 1) splits = 1;
+  if (a.k_per_split <= 0) a.k_per_split = ((a.K + kBK - 1) / kBK) * kBK;
+  const int T_ = nbm * nbn;
+  a.tile0 = 0;
+  a.ntiles = 0;
+  a.Pk = nullptr;
+  if (SHAPE == GEMM_BIG && splits == 1 && !a.tri && a.tail_ws != nullptr) {
+    static const int C = resident_blocks(KERNEL, NT);
+    const size_t es = sizeof(T) * (CPLX ? 2 : 1);
+    const int full = C > 0 ? (T_ / C) * C : T_;
+    const int R = T_ - full;
+    int S = R > 0 ? std::min(C / R, 8) : 0;
+    S = std::min(S, a.K / (2 * kBK));
+    if (R > 0 && S >= 2 && (size_t)R * S * BM * BN * es <= a.tail_ws_bytes) {
+      if (full > 0) {
+        GemmArgs b = a;
+        b.ntiles = full;
+        hipLaunchKernelGGL(KERNEL, dim3((unsigned)full, 1), dim3(NT), 0, s, b);
+      }
+      GemmArgs b = a;
+      b.tile0 = full;
+      b.ntiles = R;
+      b.Pk = a.tail_ws;
+      b.k_per_split = ((a.K + S - 1) / S + kBK - 1) / kBK * kBK;
+      hipLaunchKernelGGL(KERNEL, dim3((unsigned)R, (unsigned)S), dim3(NT), 0, s, b);
+      const int64_t elems = (int64_t)R * BM * BN;
+      hipLaunchKernelGGL((gemm_reduce_kernel<T, CPLX, BM, BN, EPI, FT>),
+                         dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, b, S);
+      return full > 0 ? 2 : 1;
+    }
+  }
+  dim3 grid((unsigned)T_, (unsigned)splits);
+  hipLaunchKernelGGL(KERNEL, grid, dim3(NT), 0, s, a);
+  return 1;
+}
+
 template <typename T, bool CPLX, bool AT, int EPI, typename FT, int SHAPE>
 static int gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   constexpr bool M3 = CPLX && SHAPE == GEMM_BIG && CHASE_CPLX_3M;
@@ -590,46 +635,23 @@ static int gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   constexpr int BK = SHAPE == GEMM_BIG ? (CPLX ? CHASE_BIG_BK_CPLX : CHASE_BIG_BK_REAL) : kBK;
   constexpr int MINB = 1;
   static_assert(kBK % BK == 0, "split granularity");
-  auto kernel = gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BK, WM, WN, EPI, FT, MINB, M3>;
-  const int nbm = (a.M + BM - 1) / BM, nbn = (a.N + BN - 1) / BN;
-  if (nbm <= 0 || nbn <= 0) return 0;
-  if (splits < 1) splits = 1;
-  if (a.k_per_split <= 0) a.k_per_split = ((a.K + kBK - 1) / kBK) * kBK;
-  const int T_ = nbm * nbn;
-  a.tile0 = 0;
-  a.ntiles = 0;
-  a.Pk = nullptr;
-  // Remainder split: the tiles beyond the last full wave of resident blocks
-  // are split along K across the idle slots of that wave; their partial sums
-  // go to the scratch and a reduce kernel applies the epilogue.
-  if (SHAPE == GEMM_BIG && splits == 1 && !a.tri && a.tail_ws != nullptr) {
-    static const int C = resident_blocks(kernel, NT);
-    const size_t es = sizeof(T) * (CPLX ? 2 : 1);
-    const int full = C > 0 ? (T_ / C) * C : T_;
-    const int R = T_ - full;
-    int S = R > 0 ? std::min(C / R, 8) : 0;
-    S = std::min(S, a.K / (2 * kBK));
-    if (R > 0 && S >= 2 && (size_t)R * S * BM * BN * es <= a.tail_ws_bytes) {
-      if (full > 0) {
-        GemmArgs b = a;
-        b.ntiles = full;
-        hipLaunchKernelGGL(kernel, dim3((unsigned)full, 1), dim3(NT), 0, s, b);
-      }
-      GemmArgs b = a;
-      b.tile0 = full;
-      b.ntiles = R;
-      b.Pk = a.tail_ws;
-      b.k_per_split = ((a.K + S - 1) / S + kBK - 1) / kBK * kBK;
-      hipLaunchKernelGGL(kernel, dim3((unsigned)R, (unsigned)S), dim3(NT), 0, s, b);
-      const int64_t elems = (int64_t)R * BM * BN;
-      hipLaunchKernelGGL((gemm_reduce_kernel<T, CPLX, BM, BN, EPI, FT>),
-                         dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s, b, S);
-      return full > 0 ? 2 : 1;
-    }
+  // direct global -> LDS loads: complex 64 x 64 three-product tiles with
+  // both operands K-contiguous and 16-byte aligned rows
+  constexpr bool DMA = CHASE_GEMM_DMA && M3 && AT && BM == 64 && BN == 64 && WM == 32 && WN == 32;
+  if constexpr (DMA) {
+    constexpr int BKD = 128 / (2 * (int)sizeof(T));
+    static_assert(kBK % BKD == 0, "split granularity");
+    const size_t es = 2 * sizeof(T);
+    const bool aligned = (uintptr_t)a.A % 16 == 0 && (uintptr_t)a.B % 16 == 0 &&
+                         ((size_t)a.lda * es) % 16 == 0 && ((size_t)a.ldb * es) % 16 == 0;
+    if (aligned)
+      return launch_tiles<gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BKD, WM, WN, EPI, FT, MINB,
+                                      M3, true>,
+                          T, CPLX, EPI, FT, SHAPE, BM, BN, NT>(a, splits, s);
   }
-  dim3 grid((unsigned)T_, (unsigned)splits);
-  hipLaunchKernelGGL(kernel, grid, dim3(NT), 0, s, a);
-  return 1;
+  return launch_tiles<gemm_kernel<T, CPLX, AT, CPLX && AT, BM, BN, BK, WM, WN, EPI, FT, MINB, M3,
+                                  false>,
+                      T, CPLX, EPI, FT, SHAPE, BM, BN, NT>(a, splits, s);
 }
 
 int gemm(bool cplx, bool prec32, bool at, bool epi_filter, bool out64, GemmShape shape,
