@@ -343,6 +343,105 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
   }
 }
 
+// Real FP64 tiles of 128 x 128 (four waves of 64 x 64), K chunks of 16
+// doubles (eight slots of two per row), two LDS stages of 32 KB fed by direct
+// loads: the next chunk streams in while the current one is multiplied (64
+// MFMAs per wave per chunk hide the load latency at two blocks per CU).
+// Loads: 1024 slots per tile, four 1 KB loads per wave per tile.
+__device__ __forceinline__ void dma_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
+                                               int wave, int lane, LdsD2 *LA, LdsD2 *LB) {
+  typedef const char __attribute__((address_space(1))) GC;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int q = 4 * wave + h;
+    const int s = 64 * q + lane;
+    const int r = s >> 3;
+    const int c = (s & 7) ^ ((r >> 1) & 7);
+    const int gi = min(m0 + r, p.M - 1);
+    const int gj = min(n0 + r, p.N - 1);
+    const GC *a = (const GC *)p.A + ((int64_t)gi * p.lda + k0 + 2 * c) * 8;
+    const GC *b = (const GC *)p.B + ((int64_t)(p.col0 + gj) * p.ldb + k0 + 2 * c) * 8;
+    __builtin_amdgcn_global_load_lds(a, LA + 64 * q, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(b, LB + 64 * q, 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void reg_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
+                                               int kend, int tid, LdsD2 *LA, LdsD2 *LB) {
+  typedef const double __attribute__((address_space(1))) GD;
+  const GD *Ag = (const GD *)p.A;
+  const GD *Bg = (const GD *)p.B;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int s = tid + 256 * t;
+    const int r = s >> 3;
+    const int c = (s & 7) ^ ((r >> 1) & 7);
+    double va[2], vb[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = k0 + 2 * c + e;
+      va[e] = (k < kend && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + k] : 0.0;
+      vb[e] = (k < kend && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + k] : 0.0;
+    }
+    LA[s] = (dbl2){va[0], va[1]};
+    LB[s] = (dbl2){vb[0], vb[1]};
+  }
+}
+
+// Same structure as dma_mainloop, two stages: chunk c waits for its own
+// loads (nothing else is in flight), barrier (every wave is done with chunk
+// c - 1, whose stage the load of chunk c + 1 reuses), issue c + 1, multiply.
+// K order inside a chunk: step 2 g + e, lane group lk multiplies element e of
+// slot column lk + 4 g, for A and B alike.
+__device__ __forceinline__ void dma_mainloop_real(const GemmArgs &p, int m0, int n0, int kbeg,
+                                                  int kend, int tid, int wm, int wn,
+                                                  d4v (&acc)[4][4], LdsD2 *__restrict__ A0,
+                                                  LdsD2 *__restrict__ B0,
+                                                  LdsD2 *__restrict__ A1,
+                                                  LdsD2 *__restrict__ B1) {
+  constexpr int BK = 16;
+  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nch = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  auto issue = [&](int c, LdsD2 *LA, LdsD2 *LB) {
+    const int k0 = kbeg + BK * c;
+    if (k0 + BK <= kend)
+      dma_chunk_real(p, m0, n0, k0, wave_u, lane, LA, LB);
+    else
+      reg_chunk_real(p, m0, n0, k0, kend, tid, LA, LB);
+  };
+  auto compute = [&](const LdsD2 *LA, const LdsD2 *LB) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int c = lk + 4 * g;
+      dbl2 va[4], vb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) va[a] = LA[dma_slot(wm * 64 + a * 16 + lr, c)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) vb[b] = LB[dma_slot(wn * 64 + b * 16 + lr, c)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::op(va[a].x, vb[b].x, acc[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::op(va[a].y, vb[b].y, acc[a][b]);
+    }
+  };
+  auto step = [&](int c, const LdsD2 *Ac, const LdsD2 *Bc, LdsD2 *An, LdsD2 *Bn) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): chunk c
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (c + 1 < nch) issue(c + 1, An, Bn);
+    compute(Ac, Bc);
+  };
+  if (nch > 0) issue(0, A0, B0);
+  for (int c = 0; c < nch; c += 2) {
+    step(c, A0, B0, A1, B1);
+    if (c + 1 < nch) step(c + 1, A1, B1, A0, B0);
+  }
+}
+
 // M3 (complex only): three real products per complex one,
 // P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2,
 // im = P3 - P1 - P2 (a quarter fewer MFMAs than the four-product form).
@@ -358,10 +457,12 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
   constexpr int NP = CPLX ? 2 : 1;
   constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
   static_assert(AE * NT == BM * BK && BE * NT == BN * BK, "tile / thread mismatch");
-  // direct-load path (the launcher checks 16-byte alignment of the operands)
+  // direct-load paths (the launcher checks 16-byte alignment of the operands)
   constexpr bool DMA = DMAP && M3 && AT && BM == 64 && BN == 64 && WM == 32 && WN == 32 &&
                        BK == 128 / (2 * (int)sizeof(T));
-  static_assert(!DMAP || DMA, "direct-load path needs 64 x 64 complex tiles, K chunks of 128 bytes");
+  constexpr bool DMAR = DMAP && !CPLX && AT && sizeof(T) == 8 && BM == 128 && BN == 128 &&
+                        WM == 64 && WN == 64 && BK == 16;
+  static_assert(!DMAP || DMA || DMAR, "no direct-load path for this tile configuration");
 
   if (p.flag != nullptr && *p.flag != 0) return;
 
@@ -409,7 +510,11 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
       }
 
   const int lr = lane & 15, lk = lane >> 4;
-  if constexpr (DMA) {
+  if constexpr (DMAR) {
+    __shared__ dbl2 R0[2][1024], R1[2][1024];
+    dma_mainloop_real(p, m0, n0, kbeg, kend, tid, wm, wn, accR, (LdsD2 *)R0[0], (LdsD2 *)R0[1],
+                      (LdsD2 *)R1[0], (LdsD2 *)R1[1]);
+  } else if constexpr (DMA) {
     __shared__ dbl2 L0[2][512], L1[2][512], L2[2][512];
     dma_mainloop<T, CONJA>(p, m0, n0, kbeg, kend, tid, wm, wn, accR, accI, acc3,
                         (LdsD2 *)L0[0], (LdsD2 *)L0[1], (LdsD2 *)L1[0], (LdsD2 *)L1[1],

@@ -638,6 +638,16 @@ static int gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   // direct global -> LDS loads: complex 64 x 64 three-product tiles with
   // both operands K-contiguous and 16-byte aligned rows
   constexpr bool DMA = CHASE_GEMM_DMA && M3 && AT && BM == 64 && BN == 64 && WM == 32 && WN == 32;
+  constexpr bool DMAR = CHASE_GEMM_DMA && !CPLX && AT && sizeof(T) == 8 && SHAPE == GEMM_BIG &&
+                        BM == 128 && BN == 128 && WM == 64 && WN == 64 && BK == 16;
+  if constexpr (DMAR) {
+    const bool aligned = (uintptr_t)a.A % 16 == 0 && (uintptr_t)a.B % 16 == 0 &&
+                         a.lda % 2 == 0 && a.ldb % 2 == 0;
+    if (aligned)
+      return launch_tiles<gemm_kernel<T, CPLX, AT, false, BM, BN, BK, WM, WN, EPI, FT, MINB, M3,
+                                      true>,
+                          T, CPLX, EPI, FT, SHAPE, BM, BN, NT>(a, splits, s);
+  }
   if constexpr (DMA) {
     constexpr int BKD = 128 / (2 * (int)sizeof(T));
     static_assert(kBK % BKD == 0, "split granularity");
