@@ -237,6 +237,53 @@ __device__ __forceinline__ void reg_chunk(const GemmArgs &p, int m0, int n0, int
   }
 }
 
+// Real FP64 tiles of 128 x 128 (four waves of 64 x 64), K chunks of 16
+// doubles (eight slots of two per row), two LDS stages of 32 KB fed by direct
+// loads: the next chunk streams in while the current one is multiplied (64
+// MFMAs per wave per chunk hide the load latency at two blocks per CU).
+// Loads: 1024 slots per tile, four 1 KB loads per wave per tile.
+__device__ __forceinline__ void dma_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
+                                               int wave, int lane, LdsD2 *LA, LdsD2 *LB) {
+  typedef const char __attribute__((address_space(1))) GC;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int q = 4 * wave + h;
+    const int s = 64 * q + lane;
+    const int r = s >> 3;
+    const int c = (s & 7) ^ ((r >> 1) & 7);
+    const int gi = min(m0 + r, p.M - 1);
+    const int gj = min(n0 + r, p.N - 1);
+    const GC *a = (const GC *)p.A + ((int64_t)gi * p.lda + k0 + 2 * c) * 8;
+    const GC *b = (const GC *)p.B + ((int64_t)(p.col0 + gj) * p.ldb + k0 + 2 * c) * 8;
+    __builtin_amdgcn_global_load_lds(a, LA + 64 * q, 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(b, LB + 64 * q, 16, 0, 0);
+  }
+}
+
+// The partial last chunk of a real FP64 tile of ROWS rows (zero fill).
+template <int ROWS = 128>
+__device__ __forceinline__ void reg_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
+                                               int kend, int tid, LdsD2 *LA, LdsD2 *LB) {
+  typedef const double __attribute__((address_space(1))) GD;
+  const GD *Ag = (const GD *)p.A;
+  const GD *Bg = (const GD *)p.B;
+#pragma unroll
+  for (int t = 0; t < ROWS / 32; ++t) {
+    const int s = tid + 256 * t;
+    const int r = s >> 3;
+    const int c = (s & 7) ^ ((r >> 1) & 7);
+    double va[2], vb[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = k0 + 2 * c + e;
+      va[e] = (k < kend && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + k] : 0.0;
+      vb[e] = (k < kend && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + k] : 0.0;
+    }
+    LA[s] = (dbl2){va[0], va[1]};
+    LB[s] = (dbl2){vb[0], vb[1]};
+  }
+}
+
 // The K loop of the direct-load path.  The six stage tiles are restrict
 // parameters of one inlined function, so the compiler knows that reading
 // stage c % 3 does not depend on the loads just issued into the other stages
@@ -245,7 +292,7 @@ __device__ __forceinline__ void reg_chunk(const GemmArgs &p, int m0, int n0, int
 // K order inside a chunk: MFMA step t, lane group lk multiplies the element
 // in slot column lk + 4 (t / EPS) (element t % EPS of the slot), the same
 // for A and B, so every k of the chunk is used once.
-template <typename T, bool CONJA>
+template <typename T, bool CONJA, bool CPLX = true>
 __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, int kbeg, int kend,
                                              int tid, int wm, int wn,
                                              typename Mfma<T>::acc (&accR)[2][2],
@@ -254,7 +301,8 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
                                              LdsD2 *__restrict__ A0, LdsD2 *__restrict__ B0,
                                              LdsD2 *__restrict__ A1, LdsD2 *__restrict__ B1,
                                              LdsD2 *__restrict__ A2, LdsD2 *__restrict__ B2) {
-  constexpr int ES = 2 * (int)sizeof(T), EPS = 16 / ES, BK = 8 * EPS;
+  constexpr int ES = (CPLX ? 2 : 1) * (int)sizeof(T), EPS = 16 / ES, BK = 8 * EPS;
+  static_assert(CPLX || sizeof(T) == 8, "real tiles of this loop are FP64");
   const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int wave_u = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nch = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
@@ -263,8 +311,10 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
     const int k0 = kbeg + BK * c;
     if (full(c))
       dma_chunk<ES>(p, m0, n0, k0, wave_u, lane, LA, LB);
-    else
+    else if constexpr (CPLX)
       reg_chunk<T>(p, m0, n0, k0, kend, tid, LA, LB);
+    else
+      reg_chunk_real<64>(p, m0, n0, k0, kend, tid, LA, LB);
   };
   auto mma = [&](const T (&ar)[2], const T (&ai)[2], const T (&br)[2], const T (&bi)[2]) {
     T as_[2], bs_[2];
@@ -285,7 +335,21 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
 #pragma unroll
     for (int g = 0; g < 2; ++g) {  // slot columns lk and lk + 4
       const int c = lk + 4 * g;
-      if constexpr (EPS == 1) {
+      if constexpr (!CPLX) {  // real FP64: two k per slot
+        dbl2 va[2], vb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) va[a] = LA[dma_slot(wm * 32 + a * 16 + lr, c)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) vb[b] = LB[dma_slot(wn * 32 + b * 16 + lr, c)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) accR[a][b] = Mfma<T>::op(va[a].x, vb[b].x, accR[a][b]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) accR[a][b] = Mfma<T>::op(va[a].y, vb[b].y, accR[a][b]);
+      } else if constexpr (EPS == 1) {
         T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
@@ -340,51 +404,6 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
     step(c, A0, B0, A2, B2);
     if (c + 1 < nch) step(c + 1, A1, B1, A0, B0);
     if (c + 2 < nch) step(c + 2, A2, B2, A1, B1);
-  }
-}
-
-// Real FP64 tiles of 128 x 128 (four waves of 64 x 64), K chunks of 16
-// doubles (eight slots of two per row), two LDS stages of 32 KB fed by direct
-// loads: the next chunk streams in while the current one is multiplied (64
-// MFMAs per wave per chunk hide the load latency at two blocks per CU).
-// Loads: 1024 slots per tile, four 1 KB loads per wave per tile.
-__device__ __forceinline__ void dma_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
-                                               int wave, int lane, LdsD2 *LA, LdsD2 *LB) {
-  typedef const char __attribute__((address_space(1))) GC;
-#pragma unroll
-  for (int h = 0; h < 4; ++h) {
-    const int q = 4 * wave + h;
-    const int s = 64 * q + lane;
-    const int r = s >> 3;
-    const int c = (s & 7) ^ ((r >> 1) & 7);
-    const int gi = min(m0 + r, p.M - 1);
-    const int gj = min(n0 + r, p.N - 1);
-    const GC *a = (const GC *)p.A + ((int64_t)gi * p.lda + k0 + 2 * c) * 8;
-    const GC *b = (const GC *)p.B + ((int64_t)(p.col0 + gj) * p.ldb + k0 + 2 * c) * 8;
-    __builtin_amdgcn_global_load_lds(a, LA + 64 * q, 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(b, LB + 64 * q, 16, 0, 0);
-  }
-}
-
-__device__ __forceinline__ void reg_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
-                                               int kend, int tid, LdsD2 *LA, LdsD2 *LB) {
-  typedef const double __attribute__((address_space(1))) GD;
-  const GD *Ag = (const GD *)p.A;
-  const GD *Bg = (const GD *)p.B;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int s = tid + 256 * t;
-    const int r = s >> 3;
-    const int c = (s & 7) ^ ((r >> 1) & 7);
-    double va[2], vb[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int k = k0 + 2 * c + e;
-      va[e] = (k < kend && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + k] : 0.0;
-      vb[e] = (k < kend && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + k] : 0.0;
-    }
-    LA[s] = (dbl2){va[0], va[1]};
-    LB[s] = (dbl2){vb[0], vb[1]};
   }
 }
 
@@ -462,7 +481,9 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
                        BK == 128 / (2 * (int)sizeof(T));
   constexpr bool DMAR = DMAP && !CPLX && AT && sizeof(T) == 8 && BM == 128 && BN == 128 &&
                         WM == 64 && WN == 64 && BK == 16;
-  static_assert(!DMAP || DMA || DMAR, "no direct-load path for this tile configuration");
+  constexpr bool DMAR64 = DMAP && !CPLX && AT && sizeof(T) == 8 && BM == 64 && BN == 64 &&
+                          WM == 32 && WN == 32 && BK == 16;
+  static_assert(!DMAP || DMA || DMAR || DMAR64, "no direct-load path for this tile configuration");
 
   if (p.flag != nullptr && *p.flag != 0) return;
 
@@ -514,6 +535,11 @@ __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(
     __shared__ dbl2 R0[2][1024], R1[2][1024];
     dma_mainloop_real(p, m0, n0, kbeg, kend, tid, wm, wn, accR, (LdsD2 *)R0[0], (LdsD2 *)R0[1],
                       (LdsD2 *)R1[0], (LdsD2 *)R1[1]);
+  } else if constexpr (DMAR64) {
+    __shared__ dbl2 L0[2][512], L1[2][512], L2[2][512];
+    dma_mainloop<T, false, false>(p, m0, n0, kbeg, kend, tid, wm, wn, accR, accR, accR,
+                                  (LdsD2 *)L0[0], (LdsD2 *)L0[1], (LdsD2 *)L1[0],
+                                  (LdsD2 *)L1[1], (LdsD2 *)L2[0], (LdsD2 *)L2[1]);
   } else if constexpr (DMA) {
     __shared__ dbl2 L0[2][512], L1[2][512], L2[2][512];
     dma_mainloop<T, CONJA>(p, m0, n0, kbeg, kend, tid, wm, wn, accR, accI, acc3,

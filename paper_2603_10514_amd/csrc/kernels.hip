@@ -639,14 +639,28 @@ static int gemm_launch(GemmArgs &a, int splits, hipStream_t s) {
   // both operands K-contiguous and 16-byte aligned rows
   constexpr bool DMA = CHASE_GEMM_DMA && M3 && AT && BM == 64 && BN == 64 && WM == 32 && WN == 32;
   constexpr bool DMAR = CHASE_GEMM_DMA && !CPLX && AT && sizeof(T) == 8 && SHAPE == GEMM_BIG &&
-                        BM == 128 && BN == 128 && WM == 64 && WN == 64 && BK == 16;
+                        ((BM == 128 && BN == 128 && WM == 64 && WN == 64) ||
+                         (BM == 64 && BN == 64 && WM == 32 && WN == 32)) && BK == 16;
   if constexpr (DMAR) {
     const bool aligned = (uintptr_t)a.A % 16 == 0 && (uintptr_t)a.B % 16 == 0 &&
                          a.lda % 2 == 0 && a.ldb % 2 == 0;
-    if (aligned)
+    if (aligned) {
+      if constexpr (BM == 128 && BN == 128) {
+        // 64 x 64 tiles instead when the 128-column padding of the output
+        // costs more than the larger tile gains (about 11% measured: real
+        // N = 20000 x 1300 runs at 60.7 against 57.2 TFLOP/s; 10000 x 300
+        // at 48.2 against 57.2) or when the matrix is small
+        const double w128 = ((a.N + 127) / 128 * 128) / (double)a.N;
+        const double w64 = ((a.N + 63) / 64 * 64) / (double)a.N;
+        if (w128 > 1.11 * w64 || a.M < 4096)
+          return launch_tiles<gemm_kernel<T, CPLX, AT, false, 64, 64, BK, 32, 32, EPI, FT, MINB,
+                                          M3, true>,
+                              T, CPLX, EPI, FT, SHAPE, 64, 64, 256>(a, splits, s);
+      }
       return launch_tiles<gemm_kernel<T, CPLX, AT, false, BM, BN, BK, WM, WN, EPI, FT, MINB, M3,
                                       true>,
                           T, CPLX, EPI, FT, SHAPE, BM, BN, NT>(a, splits, s);
+    }
   }
   if constexpr (DMA) {
     constexpr int BKD = 128 / (2 * (int)sizeof(T));

@@ -61,9 +61,13 @@ def test_filter_fp64_matches_oracle(P, gpu, N, ncols, cplx, kind):
     assert col_rel_err(out, ref) <= tol
 
 
-@pytest.mark.parametrize("cplx", [False, True])
-def test_filter_fp32_matches_oracle(P, gpu, cplx):
-    N, ncols = 1000, 60
+@pytest.mark.parametrize("N,cplx", [(1000, False), (1000, True), (1100, True), (777, True)])
+def test_filter_fp32_matches_oracle(P, gpu, N, cplx):
+    """Complex FP32 runs the direct-load loop when rows are 16-byte aligned
+    (even N; N = 1100 leaves a partial last K chunk of 12) and the
+    register-prefetch loop otherwise (N = 777)."""
+    print("fp32 filter case", N, cplx, flush=True)
+    ncols = 60
     H, lam = synth.planted_numpy(N, "dft", 6, cplx)
     V = synth.start_block(N, ncols, 7, cplx)
     deg = _degrees("mixed", ncols, np.random.default_rng(8))
@@ -198,11 +202,16 @@ def test_lanczos_first_step_full_size(P, gpu, N, cplx):
 
 
 @pytest.mark.parametrize("N,ncols,cplx,maxdeg", [(3000, 1300, True, 6), (2500, 700, False, 5),
-                                                 (20000, 64, True, 3), (9000, 200, True, 4)])
+                                                 (20000, 64, True, 3), (9000, 200, True, 4),
+                                                 (6000, 250, False, 3), (6000, 300, False, 3),
+                                                 (4101, 1030, False, 2)])
 def test_filter_remainder_split_shapes(P, gpu, N, ncols, cplx, maxdeg):
     """Shapes whose tile count leaves a partial last wave (or less than one
     wave): the remainder tiles run split along K plus a reduce kernel; the
-    result must still match the oracle column by column."""
+    result must still match the oracle column by column.  The real cases at
+    N >= 4096 cover both real tile sizes of the direct-load path (250
+    columns: 128 x 128; 300 columns: 64 x 64) and, with the odd leading
+    dimension of N = 4101, the register-prefetch path it falls back to."""
     import torch
     print("remainder-split case", N, ncols, cplx, flush=True)
     rng = np.random.default_rng(31)
