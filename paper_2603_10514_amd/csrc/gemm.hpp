@@ -7,15 +7,21 @@
 //    The filter reads H this way with A(i,k) = conj(H[k + i*ldh]) = H(i,k) for a
 //    Hermitian H, so both operands stream along contiguous columns.
 //  * B is column-major K x N: B(k,j) at B[(col0 + j)*ldb + k].
-//  * Complex products use four real MFMAs per block of 16x16 outputs
+//  * Complex products use three real MFMAs per block of 16x16 outputs on the
+//    big tiles (M3, see gemm_kernel) and four elsewhere
 //    (re = ar br - ai bi, im = ar bi + ai br).
 //  * MFMA: v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32 (FP32); both
 //    take A(i = lane%16, k = lane/16) and B(k = lane/16, j = lane%16).  The
 //    four results of a lane are D(i, j = lane%16) with i = 4*(lane/16) + r for
 //    FP32 but i = lane/16 + 4*r for FP64 (r = 0..3; measured on gfx950).
-//  * 256 threads = 4 waves in a 2 x 2 arrangement; LDS double-buffered tiles
-//    with a register prefetch of the next K chunk; tiles stored [k][i] with one
-//    element of padding so that the transposing stores are conflict-free.
+//  * 256 threads = 4 waves in a 2 x 2 arrangement.  Two K loops:
+//    - direct-load (both operands K-contiguous with 16-byte aligned rows: the
+//      filter and the Rayleigh-Ritz H Q): K chunks copied by
+//      global_load_lds_dwordx4 into a ring of LDS stages in a swizzled
+//      row layout (dma_mainloop, dma_mainloop_real);
+//    - register prefetch (everything else): LDS double-buffered tiles with a
+//      register prefetch of the next K chunk, stored [k][i] with one element
+//      of padding so that the transposing stores are conflict-free.
 //  * Block -> tile mapping is XCD aware: consecutive hardware block ids go
 //    round-robin to the 8 XCDs, so each XCD is handed a contiguous range of
 //    logical tiles, ordered in bands of tile rows (tile_coords) so that the
@@ -464,6 +470,9 @@ __device__ __forceinline__ void dma_mainloop_real(const GemmArgs &p, int m0, int
 // M3 (complex only): three real products per complex one,
 // P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2,
 // im = P3 - P1 - P2 (a quarter fewer MFMAs than the four-product form).
+// DMAP: use the direct-load K loop (complex 64 x 64 M3 tiles, real 64 x 64 or
+// 128 x 128 tiles, A K-contiguous); the launcher selects it only when both
+// operands have 16-byte aligned rows.
 template <typename T, bool CPLX, bool AT, bool CONJA, int BM, int BN, int BK, int WM, int WN,
           int EPI, typename FT, int MINB, bool M3, bool DMAP>
 __global__ __launch_bounds__(64 * (BM / WM) * (BN / WN), MINB) void gemm_kernel(const GemmArgs p) {

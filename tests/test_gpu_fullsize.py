@@ -84,3 +84,22 @@ def test_mixed_precision_full_size_n30000(gpu):
     assert np.all(out["resid"] < 1e-10)
     del H
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("N,nev,nex,fam", [(6000, 380, 120, "dft"), (10000, 200, 100, "stress")])
+def test_real_solve_large(gpu, N, nev, nex, fam):
+    """Real FP64 solves large enough for the direct-load real tiles: with
+    l = 500 the first filter steps run on 128 x 128 tiles and narrower active
+    blocks on 64 x 64; the stress spectrum is the N = 10000 workload's.
+    Eigenvalues against the planted spectrum, residuals below tol."""
+    import torch
+    import paper_2603_10514_amd as P
+    print("real large solve", N, nev, nex, fam, flush=True)
+    H, lam = synth.planted_torch(N, fam, 5, False, gpu)
+    out = P.chase_solve(H, nev, nex, 20, 1e-10, max_deg=60 if fam == "stress" else 36, seed=77)
+    torch.cuda.synchronize()
+    assert out["status"] == P.CHASE_OK
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10 * np.max(np.abs(lam))
+    assert np.all(out["resid"] < 1e-10)
+    del H
+    torch.cuda.empty_cache()
