@@ -19,6 +19,8 @@ template <> struct Num<double> {
   __device__ static double im(double) { return 0.0; }
   __device__ static double real(double r) { return r; }
   __device__ static double scale(double a, double s) { return a * s; }
+  // a + (the value of lane ^ m)
+  __device__ static double add_xor(double a, int m) { return a + __shfl_xor(a, m); }
 };
 template <> struct Num<double2> {
   __device__ static double2 zero() { return make_double2(0.0, 0.0); }
@@ -31,6 +33,9 @@ template <> struct Num<double2> {
   __device__ static double im(double2 a) { return a.y; }
   __device__ static double2 real(double r) { return make_double2(r, 0.0); }
   __device__ static double2 scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+  __device__ static double2 add_xor(double2 a, int m) {
+    return make_double2(a.x + __shfl_xor(a.x, m), a.y + __shfl_xor(a.y, m));
+  }
 };
 __device__ __forceinline__ double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 operator-(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -127,17 +132,27 @@ __global__ __launch_bounds__(256) void k_chol_diag(const E *G, int64_t ldg, E *R
     }
     __syncthreads();
   }
-  if (t < b) {  // column t of the inverse by back substitution
-    const int c = t;
-    X[c][c] = Num<E>::real(1.0 / Num<E>::re(L[c][c]));
-    for (int i = c - 1; i >= 0; --i) {
-      E s = Num<E>::zero();
-      for (int q = i + 1; q <= c; ++q) s = s + Num<E>::mul(L[i][q], X[q][c]);
-      X[i][c] = Num<E>::scale(-s, 1.0 / Num<E>::re(L[i][i]));
-    }
-    for (int i = c + 1; i < b; ++i) X[i][c] = Num<E>::zero();
-  }
+  // R^{-1} by back substitution, one row at a time from the bottom:
+  // X[i][c] = (delta_ic - sum_{q = i+1..c} R[i][q] X[q][c]) / R[i][i].  Four
+  // threads per column split each sum (every fourth q), combined by shuffles
+  // within the four consecutive lanes, so all 256 threads work on every row.
+  for (int idx = t; idx < 64 * 64; idx += 256) X[idx % 64][idx / 64] = Num<E>::zero();
   __syncthreads();
+  {
+    const int c = t >> 2, part = t & 3;
+    for (int i = b - 1; i >= 0; --i) {
+      E s = Num<E>::zero();
+      if (c < b && c > i)
+        for (int q = i + 1 + part; q <= c; q += 4) s = s + Num<E>::mul(L[i][q], X[q][c]);
+      s = Num<E>::add_xor(s, 1);
+      s = Num<E>::add_xor(s, 2);
+      if (part == 0 && c < b && c >= i) {
+        const double inv = 1.0 / Num<E>::re(L[i][i]);
+        X[i][c] = c == i ? Num<E>::real(inv) : Num<E>::scale(-s, inv);
+      }
+      __syncthreads();
+    }
+  }
   for (int idx = t; idx < b * b; idx += 256) {
     const int r = idx % b, c = idx / b;
     R[(int64_t)(p0 + c) * ldr + p0 + r] = (r <= c) ? L[r][c] : Num<E>::zero();
