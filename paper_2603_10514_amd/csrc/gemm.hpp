@@ -35,6 +35,8 @@
 //              B itself (K == M); column j goes to Ofinal when deg[j] == step
 //              (its last step, Sec. 2.2) and to Onext otherwise.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace chase {
@@ -185,19 +187,19 @@ typedef flt4 __attribute__((address_space(3))) LdsF4;
 // quarter-wave reads for a fixed c hit 16 different groups of four banks.
 __device__ __forceinline__ int dma_slot(int r, int c) { return 8 * r + (c ^ ((r >> 1) & 7)); }
 
-// One full K chunk [k0, k0 + 8 EPS) of A (rows m0..m0+63) and B (columns
-// n0..n0+63) into the tiles LA, LB: each wave issues two 1 KB loads per tile,
-// lane L of load q filling slot 64 q + L.  Rows (columns) past the matrix read
-// the last one instead: they only feed outputs that are not stored.  ES is
-// the element size in bytes, EPS = 16 / ES elements per slot.
-template <int ES>
+// One full K chunk [k0, k0 + 8 EPS) of A (rows m0..m0+ROWS-1) and B (columns
+// n0..n0+ROWS-1) into the tiles LA, LB: each wave issues ROWS / 32 loads of
+// 1 KB per tile, lane L of load q filling slot 64 q + L.  Rows (columns) past
+// the matrix read the last one instead: they only feed outputs that are not
+// stored.  ES is the element size in bytes, EPS = 16 / ES elements per slot.
+template <int ES, int ROWS>
 __device__ __forceinline__ void dma_chunk(const GemmArgs &p, int m0, int n0, int k0, int wave,
                                           int lane, LdsD2 *LA, LdsD2 *LB) {
-  constexpr int EPS = 16 / ES;
+  constexpr int EPS = 16 / ES, LPW = ROWS / 32;
   typedef const char __attribute__((address_space(1))) GC;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int q = 2 * wave + h;
+  for (int h = 0; h < LPW; ++h) {
+    const int q = LPW * wave + h;
     const int s = 64 * q + lane;
     const int r = s >> 3;
     const int c = (s & 7) ^ ((r >> 1) & 7);
@@ -211,82 +213,32 @@ __device__ __forceinline__ void dma_chunk(const GemmArgs &p, int m0, int n0, int
 }
 
 // The partial last chunk [k0, kend): ordinary loads with zero fill (k past
-// kend must contribute nothing), stored in the same layout.
-template <typename T>
+// kend must contribute nothing), packed into the same slots.  EL is the
+// element type: double, or a 2-vector (re, im) of double or float.
+template <typename EL, int ROWS>
 __device__ __forceinline__ void reg_chunk(const GemmArgs &p, int m0, int n0, int k0, int kend,
                                           int tid, LdsD2 *LA, LdsD2 *LB) {
-  typedef T __attribute__((ext_vector_type(2))) E;
-  typedef const E __attribute__((address_space(1))) GE;
-  constexpr int EPS = 16 / (int)sizeof(E);
+  typedef const EL __attribute__((address_space(1))) GE;
+  constexpr int EPS = 16 / (int)sizeof(EL);
   const GE *Ag = (const GE *)p.A;
   const GE *Bg = (const GE *)p.B;
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int s = tid + 256 * t;
-    const int r = s >> 3;
-    const int c = (s & 7) ^ ((r >> 1) & 7);
-    E va[EPS], vb[EPS];
-#pragma unroll
-    for (int e = 0; e < EPS; ++e) {
-      const int k = k0 + c * EPS + e;
-      const E z = {(T)0, (T)0};
-      va[e] = (k < kend && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + k] : z;
-      vb[e] = (k < kend && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + k] : z;
-    }
-    if constexpr (EPS == 1) {
-      LA[s] = va[0];
-      LB[s] = vb[0];
-    } else {
-      ((LdsF4 *)LA)[s] = (flt4){va[0].x, va[0].y, va[1].x, va[1].y};
-      ((LdsF4 *)LB)[s] = (flt4){vb[0].x, vb[0].y, vb[1].x, vb[1].y};
-    }
-  }
-}
-
-// Real FP64 tiles of 128 x 128 (four waves of 64 x 64), K chunks of 16
-// doubles (eight slots of two per row), two LDS stages of 32 KB fed by direct
-// loads: the next chunk streams in while the current one is multiplied (64
-// MFMAs per wave per chunk hide the load latency at two blocks per CU).
-// Loads: 1024 slots per tile, four 1 KB loads per wave per tile.
-__device__ __forceinline__ void dma_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
-                                               int wave, int lane, LdsD2 *LA, LdsD2 *LB) {
-  typedef const char __attribute__((address_space(1))) GC;
-#pragma unroll
-  for (int h = 0; h < 4; ++h) {
-    const int q = 4 * wave + h;
-    const int s = 64 * q + lane;
-    const int r = s >> 3;
-    const int c = (s & 7) ^ ((r >> 1) & 7);
-    const int gi = min(m0 + r, p.M - 1);
-    const int gj = min(n0 + r, p.N - 1);
-    const GC *a = (const GC *)p.A + ((int64_t)gi * p.lda + k0 + 2 * c) * 8;
-    const GC *b = (const GC *)p.B + ((int64_t)(p.col0 + gj) * p.ldb + k0 + 2 * c) * 8;
-    __builtin_amdgcn_global_load_lds(a, LA + 64 * q, 16, 0, 0);
-    __builtin_amdgcn_global_load_lds(b, LB + 64 * q, 16, 0, 0);
-  }
-}
-
-// The partial last chunk of a real FP64 tile of ROWS rows (zero fill).
-template <int ROWS = 128>
-__device__ __forceinline__ void reg_chunk_real(const GemmArgs &p, int m0, int n0, int k0,
-                                               int kend, int tid, LdsD2 *LA, LdsD2 *LB) {
-  typedef const double __attribute__((address_space(1))) GD;
-  const GD *Ag = (const GD *)p.A;
-  const GD *Bg = (const GD *)p.B;
 #pragma unroll
   for (int t = 0; t < ROWS / 32; ++t) {
     const int s = tid + 256 * t;
     const int r = s >> 3;
     const int c = (s & 7) ^ ((r >> 1) & 7);
-    double va[2], vb[2];
+    EL va[EPS], vb[EPS];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int k = k0 + 2 * c + e;
-      va[e] = (k < kend && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + k] : 0.0;
-      vb[e] = (k < kend && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + k] : 0.0;
+    for (int e = 0; e < EPS; ++e) {
+      const int k = k0 + c * EPS + e;
+      va[e] = (k < kend && m0 + r < p.M) ? Ag[(int64_t)(m0 + r) * p.lda + k] : EL{};
+      vb[e] = (k < kend && n0 + r < p.N) ? Bg[(int64_t)(p.col0 + n0 + r) * p.ldb + k] : EL{};
     }
-    LA[s] = (dbl2){va[0], va[1]};
-    LB[s] = (dbl2){vb[0], vb[1]};
+    dbl2 sa, sb;
+    __builtin_memcpy(&sa, va, 16);
+    __builtin_memcpy(&sb, vb, 16);
+    LA[s] = sa;
+    LB[s] = sb;
   }
 }
 
@@ -315,12 +267,11 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
   auto full = [&](int c) { return kbeg + BK * c + BK <= kend; };
   auto issue = [&](int c, LdsD2 *LA, LdsD2 *LB) {
     const int k0 = kbeg + BK * c;
+    typedef typename std::conditional<CPLX, T __attribute__((ext_vector_type(2))), T>::type EL;
     if (full(c))
-      dma_chunk<ES>(p, m0, n0, k0, wave_u, lane, LA, LB);
-    else if constexpr (CPLX)
-      reg_chunk<T>(p, m0, n0, k0, kend, tid, LA, LB);
+      dma_chunk<ES, 64>(p, m0, n0, k0, wave_u, lane, LA, LB);
     else
-      reg_chunk_real<64>(p, m0, n0, k0, kend, tid, LA, LB);
+      reg_chunk<EL, 64>(p, m0, n0, k0, kend, tid, LA, LB);
   };
   auto mma = [&](const T (&ar)[2], const T (&ai)[2], const T (&br)[2], const T (&bi)[2]) {
     T as_[2], bs_[2];
@@ -413,6 +364,10 @@ __device__ __forceinline__ void dma_mainloop(const GemmArgs &p, int m0, int n0, 
   }
 }
 
+// Real FP64 tiles of 128 x 128 (four waves of 64 x 64), K chunks of 16
+// doubles (eight slots of two per row), two LDS stages of 32 KB fed by direct
+// loads: the next chunk streams in while the current one is multiplied (64
+// MFMAs per wave per chunk hide the load latency at two blocks per CU).
 // Same structure as dma_mainloop, two stages: chunk c waits for its own
 // loads (nothing else is in flight), barrier (every wave is done with chunk
 // c - 1, whose stage the load of chunk c + 1 reuses), issue c + 1, multiply.
@@ -431,9 +386,9 @@ __device__ __forceinline__ void dma_mainloop_real(const GemmArgs &p, int m0, int
   auto issue = [&](int c, LdsD2 *LA, LdsD2 *LB) {
     const int k0 = kbeg + BK * c;
     if (k0 + BK <= kend)
-      dma_chunk_real(p, m0, n0, k0, wave_u, lane, LA, LB);
+      dma_chunk<8, 128>(p, m0, n0, k0, wave_u, lane, LA, LB);
     else
-      reg_chunk_real(p, m0, n0, k0, kend, tid, LA, LB);
+      reg_chunk<double, 128>(p, m0, n0, k0, kend, tid, LA, LB);
   };
   auto compute = [&](const LdsD2 *LA, const LdsD2 *LB) {
 #pragma unroll
