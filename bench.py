@@ -105,6 +105,7 @@ def cpu_baseline(H_dev, wl, cols, degree):
         cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
+    model, blas = host_description()
     t0 = time.perf_counter()
     ofilter.chebyshev_filter(H, V, deg, c, e, lam_lo)
     dt = time.perf_counter() - t0
@@ -114,8 +115,29 @@ def cpu_baseline(H_dev, wl, cols, degree):
     return dict(value=flops / dt / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
                 sample="oracle chebyshev_filter on %d columns x degree %d of the same N=%d matrix "
                        "(%.2f TFLOP in %.1f s); the filter is the dominant phase, so this bounds "
-                       "the oracle's whole-solve throughput from above" % (cols, degree, wl["N"],
-                                                                          flops / 1e12, dt))
+                       "the oracle's whole-solve throughput from above; host: %s, numpy BLAS %s"
+                       % (cols, degree, wl["N"], flops / 1e12, dt, model, blas))
+
+
+def host_description():
+    """(CPU model, BLAS library of numpy) of the host running the oracle."""
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        from threadpoolctl import threadpool_info
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            blas = "%s %s" % (info[0].get("internal_api", "?"), info[0].get("version", "?"))
+    except Exception:
+        pass
+    return model, blas
 
 
 def serving(args):
