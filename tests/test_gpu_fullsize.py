@@ -1,14 +1,18 @@
-"""Parity at the benchmark's full size, in the launch configuration bench.py
-times: complex Hermitian N = 20000 (DFT-like spectrum, nev 1000, nex 300,
-degrees 10-36, tol 1e-10).  The oracle cannot run the whole solve here, so
-it checks sampled outputs one by one (filter columns, residuals of sampled
-eigenpairs) and the planted spectrum gives the exact eigenvalues."""
+"""Parity at full size: the bench workload in the launch configuration
+bench.py times (complex Hermitian N = 20000, DFT-like spectrum, nev 1000,
+nex 300, degrees 10-36, tol 1e-10), the mixed-precision N = 30000 workload,
+large real solves, and a filter past 2^31 matrix elements.  The oracle
+cannot run these whole solves, so it checks sampled outputs one by one
+(filter columns, residuals of sampled eigenpairs) and the planted spectrum
+gives the exact eigenvalues."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import filter as ofilter
 from oracle import rr as orr
+
+from gpu_util import U32, U64, col_rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -103,3 +107,36 @@ def test_real_solve_large(gpu, N, nev, nex, fam):
     assert np.all(out["resid"] < 1e-10)
     del H
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("cplx,prec", [(False, 0), (True, 0), (True, 1)])
+def test_filter_64bit_indexing(gpu, cplx, prec):
+    """N = 46400 > sqrt(2^31): offsets into H pass 2^31 elements, so every
+    index into it must be 64-bit (both K loops, FP64 and FP32).  Sampled
+    columns against the oracle run on a host copy of H."""
+    import math
+    import torch
+    import paper_2603_10514_amd as P
+    N, ncols, maxdeg = 46400, 70, 2
+    print("64-bit indexing case", N, cplx, prec, flush=True)
+    dt = torch.complex128 if cplx else torch.float64
+    g = torch.Generator(device=gpu)
+    g.manual_seed(11)
+    G = torch.randn((N, N), dtype=dt, device=gpu, generator=g)
+    Hr = (G + G.conj().T) * (0.5 / math.sqrt(N))  # Hermitian, row-major
+    del G
+    A = Hr.T  # column-major storage of the Hermitian matrix conj(Hr)
+    V = synth.start_block(N, ncols, 12, cplx)
+    deg = np.sort(np.random.default_rng(13).integers(1, maxdeg + 1, ncols))
+    c, e, gam = 0.5, 1.5, -2.5
+    out = to_host(P.chase_filter(A, to_dev(V, gpu), deg, c, e, gam,
+                                 precision=P.PREC_MIXED if prec else P.PREC_FP64))
+    torch.cuda.synchronize()
+    A_host = A.cpu().numpy()  # keeps the column-major strides
+    del Hr, A
+    torch.cuda.empty_cache()
+    cols = np.unique(np.linspace(0, ncols - 1, 6).astype(int))
+    ref = ofilter.chebyshev_filter(A_host, V[:, cols], deg[cols], c, e, gam)
+    err = col_rel_err(out[:, cols], ref)
+    tol = (8.0 * maxdeg * np.sqrt(N) * U32) if prec else (4.0 * maxdeg * N * U64)
+    assert err <= tol, (err, tol)
