@@ -217,6 +217,9 @@ def main():
     ap.add_argument("--generate-only", action="store_true")
     ap.add_argument("--mixed-switch", type=float, default=None,
                     help="mixed form: switch the filter to FP64 below this residual / ||H||")
+    ap.add_argument("--mixed-buffer32", type=int, default=1, choices=[0, 1],
+                    help="mixed form, after the switch to FP64: 1 keeps the nex buffer "
+                         "columns in the FP32 filter, 0 moves the whole block to FP64")
     ap.add_argument("--qr-policy", default="auto",
                     choices=["auto", "chol1", "chol2", "shifted", "householder"],
                     help="force one QR variant every iteration (Table 3 compares "
@@ -266,6 +269,8 @@ def main():
                 qr_policy=args.qr_policy)
     if args.mixed_switch is not None:
         opts["mixed_switch"] = args.mixed_switch
+    if wl["precision"]:
+        opts["mixed_buffer32"] = args.mixed_buffer32
 
     def one(step):
         return P.chase_solve(H, nev, nex, wl["degree"], wl["tol"], evecs=evecs, seed=1000 + step,
@@ -338,7 +343,8 @@ def main():
         "config": {"workload": wl["name"], "N": N, "nev": nev, "nex": nex,
                    "degree": wl["degree"], "min_deg": wl["min_deg"], "max_deg": wl["max_deg"],
                    "tol": wl["tol"], "precision": "mixed" if wl["precision"] else "fp64",
-                   "qr_policy": args.qr_policy},
+                   "qr_policy": args.qr_policy,
+                   **({"mixed_buffer32": args.mixed_buffer32} if wl["precision"] else {})},
         "time_to_solution_s": wall / args.steps,
         "filter_tflops": flops / t_filter / 1e12,
         "filter_frac_of_per_step_roofline": t_star / t_filter,

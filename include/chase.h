@@ -72,7 +72,8 @@ typedef struct chase_iter_log {
   int32_t newly_locked;
   int32_t qr_variant;    /* chase_qr actually run (HOUSEHOLDER after fallback) */
   int32_t chol_failed;   /* 1 if a Cholesky failed and Householder QR ran       */
-  int32_t filter_prec;   /* chase_precision of this iteration's filter          */
+  int32_t filter_prec;   /* CHASE_PREC_MIXED if any column of this iteration was
+                            filtered in FP32, else CHASE_PREC_FP64             */
   int32_t deg_min, deg_max;
   int64_t matvecs;       /* sum of this iteration's degrees                    */
   double cond_est;       /* estimate (1.2) with eta = 1 (may be +inf)             */
@@ -108,6 +109,10 @@ typedef struct chase_opts {
                                 unconverged residual <= mixed_switch *
                                 max(|lambda_1|, |lambda_max|) (default 6e-5), or
                                 once an FP32 iteration fails to halve it         */
+  int32_t mixed_buffer32;    /* MIXED, after that switch: 1 (default) keeps the
+                                nex buffer columns (Ritz index >= nev among the
+                                search space) in the FP32 filter, 0 moves the
+                                whole block to FP64                              */
   void *stream;              /* hipStream_t or NULL                              */
   void (*log_cb)(const chase_iter_log *rec, void *user);
   void *log_user;
@@ -129,10 +134,11 @@ typedef struct chase_info {
   int32_t filter_launches;   /* filter GEMM kernel dispatches (one per degree
                                 step, two when the step's last partial wave is
                                 split along K)                                 */
-  int32_t filter_fp32_iters; /* iterations whose filter ran in FP32            */
+  int32_t filter_fp32_iters; /* iterations whose whole filter ran in FP32      */
   double t_total, t_filter, t_qr, t_rr, t_resid, t_lanczos; /* seconds          */
   double lambda_1, lambda_l, lambda_max; /* bounds used by the first filter     */
-  int64_t matvecs_fp32;      /* part of matvecs filtered in FP32                */
+  int64_t matvecs_fp32;      /* part of matvecs filtered in FP32 (all columns,
+                                or the buffer columns after the switch)       */
   double t_filter_fp32;      /* part of t_filter spent in FP32 filter steps     */
   double ritz_max;           /* largest Ritz value of the last Rayleigh-Ritz
                                 (the lambda_l estimate for a warm restart)      */

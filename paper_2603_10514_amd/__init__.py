@@ -60,7 +60,8 @@ class ChaseOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("lanczos_steps", ctypes.c_int32),
                 ("lanczos_nvec", ctypes.c_int32), ("lanczos_v0", ctypes.c_void_p),
                 ("inject_chol_fail_iter", ctypes.c_int32),
-                ("mixed_switch", ctypes.c_double), ("stream", ctypes.c_void_p),
+                ("mixed_switch", ctypes.c_double), ("mixed_buffer32", ctypes.c_int32),
+                ("stream", ctypes.c_void_p),
                 ("log_cb", LOG_CB), ("log_user", ctypes.c_void_p),
                 ("block_cb", BLOCK_CB), ("block_user", ctypes.c_void_p)]
 

@@ -116,6 +116,7 @@ void chase_opts_default(chase_opts *o) {
   o->lanczos_nvec = 4;
   o->inject_chol_fail_iter = -1;
   o->mixed_switch = 6e-5;
+  o->mixed_buffer32 = 1;
 }
 
 chase_status chase_solve(const void *H, int64_t N, int64_t ldh, int32_t nev, int32_t nex,

@@ -695,19 +695,6 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
   for (it = 1; it <= o.max_iter; ++it) {
     const double cc = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
     const int Lp = L - k;
-    // degree-sorted order of the active columns (stable)
-    std::vector<int> order(Lp);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m[a] < m[b]; });
-    std::vector<int> msorted(Lp);
-    for (int a = 0; a < Lp; ++a) {
-      msorted[a] = m[order[a]];
-      w.h_ints[a] = order[a] + k;
-    }
-    CHASE_HIP(hipMemcpyAsync(w.perm, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
-    CHASE_HIP(hipStreamSynchronize(s));  // h_ints is reused below
-    for (int a = 0; a < Lp; ++a) w.h_ints[a] = msorted[a];
-    CHASE_HIP(hipMemcpyAsync(w.deg, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
     if (mixed && !theta_act.empty()) {
       // FP32 while the residuals are above the switch point and still fall:
       // an FP32 pass that does not halve the lowest unconverged residual has
@@ -717,11 +704,40 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
       rmin_prev = rmin;
     }
     const bool f32 = mixed && filter32;
-    gather_cols(cplx, f32, evecs, ldv, w.X0, N, (int)N, Lp, w.perm, s);
+    // after the switch, MIXED keeps the buffer columns (Ritz index >= nev - k
+    // among the active ones) in FP32: they need not converge, and the
+    // Rayleigh-Ritz step on the whole block only gains from them
+    const int nW = (mixed && !filter32 && o.mixed_buffer32) ? nev - k : Lp;
+    // degree-sorted order of the active columns (stable), within each group
+    std::vector<int> order(Lp);
+    std::iota(order.begin(), order.end(), 0);
+    auto by_degree = [&](int a, int b) { return m[a] < m[b]; };
+    std::stable_sort(order.begin(), order.begin() + nW, by_degree);
+    std::stable_sort(order.begin() + nW, order.end(), by_degree);
+    std::vector<int> msorted(Lp);
+    for (int a = 0; a < Lp; ++a) {
+      msorted[a] = m[order[a]];
+      w.h_ints[a] = order[a] + k;
+    }
+    CHASE_HIP(hipMemcpyAsync(w.perm, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
+    CHASE_HIP(hipStreamSynchronize(s));  // h_ints is reused below
+    for (int a = 0; a < Lp; ++a) w.h_ints[a] = msorted[a];
+    CHASE_HIP(hipMemcpyAsync(w.deg, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
     void *bufs[3] = {w.X0, w.B1, w.B2};
+    gather_cols(cplx, f32, evecs, ldv, w.X0, N, (int)N, nW, w.perm, s);
     CHASE_HIP(hipEventRecord(c.ev[0], s));
-    const int nl = filter(c, cplx, f32, f32 ? w.H32 : H, f32 ? N : ldh, N, bufs, N, Lp, w.deg,
-                          msorted, cc, e, gamma, (char *)w.Xq + es * (size_t)k * N, N);
+    const std::vector<int> msW(msorted.begin(), msorted.begin() + nW);
+    int nl = filter(c, cplx, f32, f32 ? w.H32 : H, f32 ? N : ldh, N, bufs, N, nW, w.deg, msW, cc,
+                    e, gamma, (char *)w.Xq + es * (size_t)k * N, N);
+    CHASE_HIP(hipEventRecord(c.ev[5], s));
+    int64_t mv32 = 0;
+    if (nW < Lp) {  // the buffer columns through the FP32 filter
+      const std::vector<int> msB(msorted.begin() + nW, msorted.end());
+      gather_cols(cplx, true, evecs, ldv, w.X0, N, (int)N, Lp - nW, w.perm + nW, s);
+      nl += filter(c, cplx, true, w.H32, N, N, bufs, N, Lp - nW, w.deg + nW, msB, cc, e, gamma,
+                   (char *)w.Xq + es * (size_t)(k + nW) * N, N);
+      for (int v : msB) mv32 += v;
+    }
     CHASE_HIP(hipEventRecord(c.ev[1], s));
     inf.filter_launches += nl;
     if (f32) inf.filter_fp32_iters++;
@@ -760,7 +776,13 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     rec.t_rr = elapsed(c.ev[2], c.ev[3]);
     rec.t_resid = elapsed(c.ev[3], c.ev[4]);
     inf.t_filter += rec.t_filter; inf.t_qr += rec.t_qr; inf.t_rr += rec.t_rr;
-    if (f32) { inf.t_filter_fp32 += rec.t_filter; inf.matvecs_fp32 += mv; }
+    if (f32) {
+      inf.t_filter_fp32 += rec.t_filter;
+      inf.matvecs_fp32 += mv;
+    } else if (mv32 > 0) {
+      inf.t_filter_fp32 += elapsed(c.ev[5], c.ev[1]);
+      inf.matvecs_fp32 += mv32;
+    }
     inf.t_resid += rec.t_resid;
     std::vector<double> th(w.h_theta, w.h_theta + Lp), rr(w.h_resid, w.h_resid + Lp);
     int j = k;
@@ -768,7 +790,8 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     const int newly = j - k;
     for (int a = 0; a < newly; ++a) { lam.push_back(th[a]); res_locked.push_back(rr[a]); }
     rec.iter = it; rec.locked = k; rec.newly_locked = newly; rec.qr_variant = q.ran;
-    rec.chol_failed = q.failed; rec.filter_prec = f32 ? CHASE_PREC_MIXED : CHASE_PREC_FP64;
+    rec.chol_failed = q.failed;
+    rec.filter_prec = (f32 || mv32 > 0) ? CHASE_PREC_MIXED : CHASE_PREC_FP64;
     rec.deg_min = mmin; rec.deg_max = mmax; rec.matvecs = mv; rec.cond_est = est;
     rec.cond_exact = kappa;
     rec.ncols = Lp;

@@ -152,6 +152,27 @@ def test_mixed_precision_matches_fp64_oracle(P, gpu, cplx, family):
     assert out["info"]["matvecs_fp32"] > 0
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_mixed_buffer_columns_stay_fp32(P, gpu, cplx):
+    """MIXED after the switch to FP64: with mixed_buffer32 the nex buffer
+    columns keep the FP32 filter.  Both settings reach the FP64 oracle's
+    eigenvalues to 1e-10 relative; the default filters more MatVecs in FP32
+    and logs partly-FP32 iterations after the switch."""
+    N, nev, nex = (1200, 60, 24) if not cplx else (900, 45, 18)
+    H, lam = synth.planted_numpy(N, "dft", 41, cplx)
+    ref, on = _run(P, gpu, H, lam, nev, nex, cplx, 42, precision=P.PREC_MIXED)
+    _, off = _run(P, gpu, H, lam, nev, nex, cplx, 42, precision=P.PREC_MIXED, mixed_buffer32=0)
+    scale = np.max(np.abs(lam))
+    for out in (on, off):
+        assert out["status"] == P.CHASE_OK
+        assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10 * scale
+        assert np.all(out["resid"] < 1e-10)
+    n_mixed = sum(r["filter_prec"] == P.PREC_MIXED for r in on["log"])
+    assert n_mixed > on["info"]["filter_fp32_iters"] >= 1
+    assert on["info"]["matvecs_fp32"] > off["info"]["matvecs_fp32"]
+    assert sum(r["filter_prec"] == P.PREC_MIXED for r in off["log"]) == off["info"]["filter_fp32_iters"]
+
+
 def test_exact_condition_number_logged(P, gpu):
     """Sec. 4.3: the estimate against the exact kappa_2 of [Y, filtered],
     per iteration, on the GPU and in the oracle."""
