@@ -26,7 +26,9 @@ Parity status per module (the pins live in ``tests/test_oracle_*.py``):
              values; Table 1 validity ranges; LAPACK Householder QR)
   rr         pinned (full diagonalisation of planted spectra)
   solver     pinned (planted eigenvalues, full diagonalisation, residual bound)
-  degrees    parity unpinned (the paper gives no formula; see its docstring)
+  degrees    pinned by a property (the predicted degree reaches tol on a
+             planted diagonal case, one degree fewer does not); the formula
+             and its margin are a reading (the paper gives none)
   lanczos    pinned in part (Gauss-quadrature weights on a matrix with three
              distinct eigenvalues; top Ritz pair and its residual against a
              Rayleigh-Ritz on an independently built Krylov basis; the

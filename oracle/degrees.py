@@ -2,9 +2,12 @@
 
 Oracle module (test infrastructure only).
 
-PARITY UNPINNED: the paper says each vector is filtered with a degree "just
-high enough" to converge within the tolerance, with the initial degree 20 and
-a cap of 36 in its experiments, but gives no formula.  The reading used here:
+The paper says each vector is filtered with a degree "just high enough" to
+converge within the tolerance, with the initial degree 20 and a cap of 36 in
+its experiments, but gives no formula.  Pinned by a property, not by the
+paper (tests: the predicted degree brings a vector whose unwanted components
+lie in the damped interval to tol, and one degree fewer than the bare
+prediction does not); the margin of 2 is a reading.  The reading used here:
 a column whose residual is r and whose Ritz value has convergence ratio
 1/|rho| needs about ln(r/tol)/ln|rho| more filter steps, so
 m_a = ceil(ln(r_a/tol) / ln|rho(theta_a)|) + margin, clamped to

@@ -23,7 +23,7 @@ Readings of points the paper leaves open (each is listed in the design notes):
     normalisation at the lowest locked value the filtered columns shrink by
     (|rho_{k+1}|/|rho_1|)^m against the unit-norm locked ones and kappa_2
     grows to about |rho_1|^m;
-  * degrees: see ``degrees.py`` (parity unpinned).
+  * degrees: see ``degrees.py`` (a reading pinned by a property).
 """
 from dataclasses import dataclass, field
 

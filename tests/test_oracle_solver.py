@@ -11,6 +11,7 @@ import scipy.linalg as sla
 
 import synth
 from oracle import degrees, lanczos, rr, solver
+from oracle import filter as ofilter
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
 
@@ -201,6 +202,40 @@ def test_lanczos_tridiagonal_reproduces_krylov_basis():
     T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
     # a full run (k = N) has the whole spectrum
     assert np.allclose(np.sort(sla.eigvalsh(T)), lam, atol=1e-10)
+
+
+@pytest.mark.parametrize("lam1", [-1.5, -1.1, -3.0])
+@pytest.mark.parametrize("delta", [1e-2, 1e-4, 1e-6])
+def test_degree_rule_reaches_tol(lam1, delta):
+    """What the degree rule predicts: a vector with residual r whose unwanted
+    components lie in the damped interval loses a factor |rho(theta)| per
+    filter step (Chebyshev growth outside [-1, 1], Sec. 2.1), so the
+    predicted degree brings its residual to tol.  Diagonal H, wanted
+    eigenvalue lam1 below the damped interval [0, 2]; the filtered vector's
+    residual is recomputed from its own Rayleigh quotient."""
+    rng = np.random.default_rng(int(abs(lam1) * 10) + int(-np.log10(delta)))
+    N, tol = 300, 1e-10
+    lam = np.concatenate([[lam1], np.sort(rng.uniform(0.0, 2.0, N - 1))])
+    H = np.diag(lam)
+
+    def resid(x):
+        x = x / np.linalg.norm(x)
+        th = float(x @ (H @ x))
+        return th, float(np.linalg.norm(H @ x - th * x))
+
+    w = rng.standard_normal(N)
+    w[0] = 0.0
+    v = np.zeros(N)
+    v[0] = 1.0
+    v = v + delta * w / np.linalg.norm(w)
+    th, r = resid(v)
+    c, e = 1.0, 1.0
+    m = int(degrees.optimised_degrees(np.array([th]), np.array([r]), tol, c, e, 1, 200)[0])
+    r_at = {mm: resid(ofilter.chebyshev_filter(H, v[:, None], np.array([mm]), c, e, th)[:, 0])[1]
+            for mm in (m - 3, m - 2, m)}
+    assert r_at[m] <= tol                 # the rule with its margin of 2
+    assert r_at[m - 2] <= 2.0 * tol       # the bare prediction: tol within T_m ~ |rho|^m / 2
+    assert r_at[m - 3] > 0.1 * tol        # and not more than one degree to spare
 
 
 def test_degrees_rule():
