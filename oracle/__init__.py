@@ -29,11 +29,12 @@ Parity status per module (the pins live in ``tests/test_oracle_*.py``):
   degrees    pinned by a property (the predicted degree reaches tol on a
              planted diagonal case, one degree fewer does not); the formula
              and its margin are a reading (the paper gives none)
-  lanczos    pinned in part (Gauss-quadrature weights on a matrix with three
-             distinct eigenvalues; top Ritz pair and its residual against a
-             Rayleigh-Ritz on an independently built Krylov basis; the
-             upper-bound property); the choice of the lambda_l estimate is
-             parity unpinned (the paper gives no details of its estimator)
+  lanczos    pinned by properties (Gauss-quadrature weights on a matrix
+             with three distinct eigenvalues; top Ritz pair and its residual
+             against a Rayleigh-Ritz on an independently built Krylov basis;
+             the upper-bound property; the run-averaged density count
+             against the eigenvalue count); the estimator itself is a
+             reading (the paper gives no details of it)
 """
 
 from .chebyshev import cheb_closed, rho_abs, sigma_sequence, scaled_poly_recurrence

@@ -5,8 +5,9 @@ Oracle module (test infrastructure only).
 
 The paper fixes one property only: the estimate of lambda_n must bound the
 spectrum from above, while the estimates of lambda_1 and lambda_l may be
-rough.  Reading used here (pinned by the properties in the tests, otherwise
-PARITY UNPINNED):
+rough.  Reading used here (pinned by properties in the tests: Gauss weights,
+the top Ritz pair's residual, the upper-bound property, and the density
+count against the eigenvalue count):
 
 * nvec independent runs, one per start vector, each k steps with full
   reorthogonalisation; run r gives T_k = tridiag(beta, alpha, beta) with

@@ -170,6 +170,24 @@ def test_lanczos_gauss_weights_three_eigenvalues():
     assert low == pytest.approx(-1.5, abs=1e-12) and up == pytest.approx(2.0, abs=1e-12)
 
 
+def test_lanczos_density_count_tracks_eigenvalue_count():
+    """The lambda_l estimate reads the run-averaged count (1/nvec) sum_r
+    sum_{theta_rj <= x} N |e_1^T s_rj|^2, an unbiased estimate of the
+    number of eigenvalues <= x (E N |q_i^H v|^2 = 1 for a random unit v).
+    With 32 full-length runs the estimate lands within a few eigenvalues of
+    lambda_l; with 40 steps, within the coarser quadrature resolution."""
+    N = 200
+    H, lam = synth.planted_numpy(N, "uniform", 9)
+    V0 = synth.lanczos_starts(N, 32, 10)
+    full = [lanczos.lanczos_tridiag(H, V0[:, r], N) for r in range(32)]
+    short = [lanczos.lanczos_tridiag(H, V0[:, r], 40) for r in range(32)]
+    for L in (20, 60, 120):
+        j_full = int(np.sum(lam <= lanczos.bounds_from_runs(full, N, L)[1] + 1e-12))
+        j_short = int(np.sum(lam <= lanczos.bounds_from_runs(short, N, L)[1] + 1e-12))
+        assert abs(j_full - L) <= 4, (L, j_full)
+        assert abs(j_short - L) <= 0.1 * L + 2, (L, j_short)
+
+
 @pytest.mark.parametrize("cplx", [False, True])
 def test_lanczos_top_pair_against_krylov_rayleigh_ritz(cplx):
     """The largest Ritz value of T_k and |beta_k||e_k^T s_max| equal the
