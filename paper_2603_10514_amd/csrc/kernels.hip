@@ -357,6 +357,241 @@ __global__ void k_sum_splits_diag(const E *P, int nsplit, int64_t sstride, int64
   out[(int64_t)c * ldo + q] = s;
 }
 
+// ------------------------------------------------- Householder QR (HHQR) --
+// Blocked Householder QR in the geqrf convention: reflector j is
+// H_j = I - tau_j v_j v_j^H with v_j(j) = 1, chosen so that
+// H_j^H (alpha, x) = (beta, 0) with beta real (beta = -sign(Re alpha) *
+// ||(alpha, x)||; tau = 0 when x = 0 and alpha is real).  The hh_state
+// buffer holds, twice (alternating column steps), the row of the pivot and
+// the per-block partial sums of a column step (offsets below).
+constexpr int kHhMaxBlocks = 256;  // row blocks of one column launch
+constexpr size_t kHhRow = 0, kHhPart = 2 * 16 * kHhNB,
+                 kHhPartBytes = 8 * (size_t)kHhMaxBlocks * 2 * kHhNB;
+static_assert(kHhPart + 2 * kHhPartBytes <= kHhStateBytes, "hh_state size");
+
+template <typename E> __device__ __forceinline__ E recip(E a);
+template <> __device__ __forceinline__ double recip(double a) { return 1.0 / a; }
+template <> __device__ __forceinline__ double2 recip(double2 a) {
+  const double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+
+// One column step of the panel factorisation.  P is the panel (Mp x nbp,
+// column-major, leading dimension ld) from the diagonal element of its first
+// column down; Vb the same block of the explicit reflector store (zero on
+// entry above the diagonal); tau the panel's tau entries.  Launch jj
+// (0 <= jj <= nbp):
+//  * jj >= 1 forms reflector jj-1 from the previous launch's block sums
+//    (nprev blocks, added in block order by every block, so all agree):
+//    beta (written to P[jj-1, jj-1]), tau, the scale 1 / (alpha - beta) and
+//    w_c = v^H P[:, c]; scales the vector below the unit diagonal, stores it
+//    in P and Vb, and applies H^H to columns jj..nbp-1;
+//  * jj < nbp writes this block's sums s_c = sum_{r > jj} conj(P[r, jj])
+//    P[r, c] (c = jj..nbp-1) and, from the block holding row jj, that row.
+// Nothing waits on another block: the launch boundary orders the steps.
+// Each wave reduces its NB accumulators by a halving exchange that leaves
+// accumulator `lane` in lane `lane` (63 exchanges instead of 6 per value).
+template <typename E, int NB>
+__global__ __launch_bounds__(256) void k_hh_column(E *__restrict__ P, int64_t ld, int Mp, int nbp,
+                                                   int jj, int nprev, E *__restrict__ Vb,
+                                                   int64_t ldv, E *__restrict__ tau, char *hs) {
+  constexpr int ES = sizeof(E) / sizeof(double);
+  constexpr int D = NB * ES;  // doubles summed per row
+  static_assert(D <= 64 && (D & (D - 1)) == 0, "one wave reduces the sums");
+  const E *rowp = (const E *)(hs + kHhRow) + ((jj + 1) & 1) * NB;
+  E *rowc = (E *)(hs + kHhRow) + (jj & 1) * NB;
+  const double *partp = (const double *)(hs + kHhPart + ((jj + 1) & 1) * kHhPartBytes);
+  double *partc = (double *)(hs + kHhPart + (jj & 1) * kHhPartBytes);
+  __shared__ E s_w[NB];
+  __shared__ E s_ct, s_sc;
+  __shared__ double s_red[4][64];
+  __shared__ double s_sum[64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const bool upd = jj >= 1, fact = jj < nbp;
+  if (upd) {
+    const int p = jj - 1;  // the reflector formed here
+    {  // thread (g, q) adds the sums of blocks g, g + G, ... for entry q, eight loads at a time
+      constexpr int G = 256 / D;
+      const int q = t % D, g = t / D;
+      double v = 0.0;
+      for (int b0 = g; b0 < nprev; b0 += 8 * G) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int b = b0 + u * G;
+          x[u] = b < nprev ? partp[(int64_t)b * D + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+      }
+      s_red[g * D / 64][(g * D) % 64 + q] = v;
+    }
+    __syncthreads();
+    if (t < D) {
+      constexpr int G = 256 / D;
+      double v = 0.0;
+      for (int g = 0; g < G; ++g) v += s_red[g * D / 64][(g * D) % 64 + t];
+      s_sum[t] = v;
+    }
+    __syncthreads();
+    if (t == 0) {
+      const E alpha = rowp[p];
+      const double xn2 = s_sum[ES * p];
+      E tv = Num<E>::zero(), sc = Num<E>::zero();
+      double beta = Num<E>::re(alpha);
+      if (xn2 != 0.0 || Num<E>::im(alpha) != 0.0) {
+        beta = -copysign(sqrt(Num<E>::abs2(alpha) + xn2), Num<E>::re(alpha));
+        tv = Num<E>::scale(Num<E>::real(beta) - alpha, 1.0 / beta);
+        sc = recip(alpha - Num<E>::real(beta));
+      }
+      s_ct = Num<E>::cj(tv);
+      s_sc = sc;
+      if (blockIdx.x == 0) {
+        tau[p] = tv;
+        P[p + p * ld] = Num<E>::real(beta);
+      }
+    }
+    __syncthreads();
+    if (t > p && t < nbp) {
+      E sv;
+      if constexpr (ES == 2) sv = make_double2(s_sum[2 * t], s_sum[2 * t + 1]);
+      else sv = s_sum[t];
+      s_w[t] = rowp[t] + Num<E>::mul(Num<E>::cj(s_sc), sv);
+    }
+    __syncthreads();
+  }
+  double acc[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) acc[i] = 0.0;
+  const int rbeg = upd ? jj - 1 : 0;
+  for (int64_t r = rbeg + (int64_t)blockIdx.x * 256 + t; r < Mp; r += (int64_t)gridDim.x * 256) {
+    // all loads of the row first and without branches, so that they are in
+    // flight together: columns outside jj..nbp-1 load a valid column and are
+    // ignored; row jj-1 of column jj-1 (beta, being written by block 0) is
+    // replaced by Vb's zero
+    const E xprev = upd ? *(r > jj - 1 ? &P[r + (jj - 1) * ld] : &Vb[r + (jj - 1) * ldv])
+                        : Num<E>::zero();
+    E pv[NB];
+    if (fact) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) pv[c] = P[r + min(max(c, jj), nbp - 1) * ld];
+    }
+    E cv = Num<E>::zero();  // conj(tau) v_r of reflector jj-1
+    if (upd) {
+      const E v = r > jj - 1 ? Num<E>::mul(xprev, s_sc) : Num<E>::real(1.0);
+      if (r > jj - 1) P[r + (jj - 1) * ld] = v;
+      Vb[r + (jj - 1) * ldv] = v;
+      cv = Num<E>::mul(s_ct, v);
+    }
+    if (!fact) continue;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (upd && c >= jj && c < nbp) {
+        pv[c] = pv[c] - Num<E>::mul(cv, s_w[c]);
+        P[r + c * ld] = pv[c];
+      }
+    const bool lead = r == jj;
+    E x = Num<E>::zero();
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c == jj && r > jj) x = Num<E>::cj(pv[c]);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c >= jj && c < nbp) {
+        if (lead) rowc[c] = pv[c];
+        const E y = Num<E>::mul(x, pv[c]);
+        acc[ES * c] += Num<E>::re(y);
+        if (ES == 2) acc[ES * c + ES - 1] += Num<E>::im(y);
+      }
+    }
+  }
+  if (!fact) return;
+  // wave reduction: fold to D lanes' worth, then halve the set per exchange
+#pragma unroll
+  for (int m = 32; m >= D; m >>= 1)
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[i] += __shfl_xor(acc[i], m);
+#pragma unroll
+  for (int h = D / 2; h >= 1; h >>= 1) {
+    const bool up = (lane & h) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double send = up ? acc[i] : acc[i + h];
+      const double keep = up ? acc[i + h] : acc[i];
+      acc[i] = keep + __shfl_xor(send, h);
+    }
+  }
+  __syncthreads();           // s_red is reused
+  s_red[wave][lane] = acc[0];  // lane holds accumulator lane % D
+  __syncthreads();
+  if (t < D) partc[(int64_t)blockIdx.x * D + t] = s_red[0][t] + s_red[1][t] + s_red[2][t] + s_red[3][t];
+}
+
+// T (nb x nb, upper triangular) of the compact WY form H_0 ... H_{nb-1} =
+// I - V T V^H from S = V^H V and tau: T[i][i] = tau_i and
+// T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i].  One packed upper triangle in
+// LDS holds S, and column i of T replaces column i of S once computed
+// (column i of T reads only T's earlier columns and S's column i).  Thread t
+// owns row t.
+template <typename E>
+__global__ __launch_bounds__(kHhMaxOuter) void k_hh_larft(const E *S, int64_t lds, const E *tau,
+                                                          E *T, int64_t ldt, int nb) {
+  __shared__ E sh[kHhMaxOuter * (kHhMaxOuter + 1) / 2];  // (k, i), k <= i, at i (i + 1) / 2 + k
+  const int t = threadIdx.x;
+  for (int i0 = 0; i0 < nb; i0 += 8) {  // eight loads in flight per thread
+    E x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = i0 + u < nb && t <= i0 + u ? S[t + (i0 + u) * lds] : Num<E>::zero();
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < nb && t <= i0 + u) sh[(i0 + u) * (i0 + u + 1) / 2 + t] = x[u];
+  }
+  __syncthreads();
+  for (int i = 0; i < nb; ++i) {
+    E v = Num<E>::zero();
+    if (t < i) {
+      const E *si = sh + i * (i + 1) / 2;
+      E v1 = Num<E>::zero(), v2 = Num<E>::zero(), v3 = Num<E>::zero();
+      int k = t;
+      for (; k + 3 < i; k += 4) {  // four chains in flight
+        v = v + Num<E>::mul(sh[k * (k + 1) / 2 + t], si[k]);
+        v1 = v1 + Num<E>::mul(sh[(k + 1) * (k + 2) / 2 + t], si[k + 1]);
+        v2 = v2 + Num<E>::mul(sh[(k + 2) * (k + 3) / 2 + t], si[k + 2]);
+        v3 = v3 + Num<E>::mul(sh[(k + 3) * (k + 4) / 2 + t], si[k + 3]);
+      }
+      for (; k < i; ++k) v = v + Num<E>::mul(sh[k * (k + 1) / 2 + t], si[k]);
+      v = -Num<E>::mul(tau[i], (v + v1) + (v2 + v3));
+    } else if (t == i) {
+      v = tau[i];
+    }
+    __syncthreads();
+    if (t <= i) sh[i * (i + 1) / 2 + t] = v;
+    __syncthreads();
+  }
+  for (int i = 0; i < nb; ++i)
+    if (t < nb) T[t + i * ldt] = t <= i ? sh[i * (i + 1) / 2 + t] : Num<E>::zero();
+}
+
+// out (rows x cols) = sum over nsplit partials (fixed order).
+template <typename E>
+__global__ void k_sum_splits(const E *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
+                             E *out, int64_t ldo) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= rows) return;
+  const int64_t c = blockIdx.y;
+  E s = Num<E>::zero();
+  for (int p = 0; p < nsplit; ++p) s = s + P[p * sstride + c * ldp + q];
+  out[c * ldo + q] = s;
+}
+
+// A (rows x cols) = the first cols columns of the identity.
+template <typename E> __global__ void k_set_identity(E *A, int64_t lda, int rows) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows) return;
+  const int64_t j = blockIdx.y;
+  A[i + j * lda] = Num<E>::real(i == j ? 1.0 : 0.0);
+}
+
 // ========================================================== launchers ==
 static inline unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
@@ -550,6 +785,57 @@ void sum_splits_diag(bool cplx, const void *P, int nsplit, int64_t sstride, int6
   else
     hipLaunchKernelGGL(k_sum_splits_diag<double>, grid, dim3(256), 0, s, (const double *)P, nsplit,
                        sstride, ldp, rows, nv, (double *)out, ldo);
+}
+
+static unsigned hh_blocks(int Mp, int jj) {
+  const int rbeg = jj >= 1 ? jj - 1 : 0;
+  return std::min<unsigned>(kHhMaxBlocks, blocks(Mp - rbeg, 256));
+}
+
+void hh_column(bool cplx, void *P, int64_t ld, int Mp, int nbp, int jj, void *Vb, int64_t ldv,
+               void *tau, void *hh_state, hipStream_t s) {
+  if (nbp < 1 || nbp > kHhNB || jj < 0 || jj > nbp || Mp < nbp) throw InvalidArg();
+  const unsigned nblk = hh_blocks(Mp, jj);
+  const int nprev = jj >= 1 ? (int)hh_blocks(Mp, jj - 1) : 0;
+  if (cplx)
+    hipLaunchKernelGGL((k_hh_column<double2, kHhNB>), dim3(nblk), dim3(256), 0, s, (double2 *)P,
+                       ld, Mp, nbp, jj, nprev, (double2 *)Vb, ldv, (double2 *)tau,
+                       (char *)hh_state);
+  else
+    hipLaunchKernelGGL((k_hh_column<double, kHhNB>), dim3(nblk), dim3(256), 0, s, (double *)P, ld,
+                       Mp, nbp, jj, nprev, (double *)Vb, ldv, (double *)tau, (char *)hh_state);
+}
+
+void hh_larft(bool cplx, const void *S, int64_t lds, const void *tau, void *T, int64_t ldt,
+              int nb, hipStream_t s) {
+  if (nb < 1 || nb > kHhMaxOuter) throw InvalidArg();
+  if (cplx)
+    hipLaunchKernelGGL(k_hh_larft<double2>, dim3(1), dim3(kHhMaxOuter), 0, s, (const double2 *)S,
+                       lds, (const double2 *)tau, (double2 *)T, ldt, nb);
+  else
+    hipLaunchKernelGGL(k_hh_larft<double>, dim3(1), dim3(kHhMaxOuter), 0, s, (const double *)S,
+                       lds, (const double *)tau, (double *)T, ldt, nb);
+}
+
+void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
+                int cols, void *out, int64_t ldo, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 grid(blocks(rows, 256), cols);
+  if (cplx)
+    hipLaunchKernelGGL(k_sum_splits<double2>, grid, dim3(256), 0, s, (const double2 *)P, nsplit,
+                       sstride, ldp, rows, (double2 *)out, ldo);
+  else
+    hipLaunchKernelGGL(k_sum_splits<double>, grid, dim3(256), 0, s, (const double *)P, nsplit,
+                       sstride, ldp, rows, (double *)out, ldo);
+}
+
+void set_identity(bool cplx, void *A, int64_t lda, int rows, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 grid(blocks(rows, 256), cols);
+  if (cplx)
+    hipLaunchKernelGGL(k_set_identity<double2>, grid, dim3(256), 0, s, (double2 *)A, lda, rows);
+  else
+    hipLaunchKernelGGL(k_set_identity<double>, grid, dim3(256), 0, s, (double *)A, lda, rows);
 }
 
 // ------------------------------------------------------------- GEMM ------

@@ -60,4 +60,22 @@ void norm_scale_cols(bool cplx, const void *w, int64_t ldw, int n, int ncols, vo
 void sum_splits_diag(bool cplx, const void *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
                      int nv, void *out, int64_t ldo, hipStream_t s);
 
+// Householder QR helpers (geqrf convention, panels of kHhNB columns).
+constexpr int kHhNB = 32;         // columns of one panel of column steps
+constexpr int kHhMaxOuter = 128;  // columns of one block reflector (T at most this wide)
+constexpr size_t kHhStateBytes = (size_t)320 << 10;  // pivot rows, block sums (two each)
+// One column step jj (0..nbp) of the panel P (Mp x nbp from its first
+// diagonal element); Vb receives the explicit reflector vectors, tau the
+// panel's tau entries.  Step jj + 1 reads what step jj left in hh_state, so
+// the steps of one panel run in order on one stream.
+void hh_column(bool cplx, void *P, int64_t ld, int Mp, int nbp, int jj, void *Vb, int64_t ldv,
+               void *tau, void *hh_state, hipStream_t s);
+// T (nb x nb, nb <= kHhMaxOuter) of the compact WY form from S = V^H V and tau.
+void hh_larft(bool cplx, const void *S, int64_t lds, const void *tau, void *T, int64_t ldt,
+              int nb, hipStream_t s);
+// out (rows x cols) = sum of nsplit partials.
+void sum_splits(bool cplx, const void *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
+                int cols, void *out, int64_t ldo, hipStream_t s);
+void set_identity(bool cplx, void *A, int64_t lda, int rows, int cols, hipStream_t s);
+
 }  // namespace chase

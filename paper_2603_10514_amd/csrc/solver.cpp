@@ -201,6 +201,7 @@ static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int 
       k ? al(es * (size_t)lzs * k * nv * nv) : 0,                         // LhP
       k ? al(16 * (size_t)k * nv) : 0,                                    // lz_ab
       al(kTailScratch),                                                   // SK
+      al(kHhStateBytes),                                                  // hh
   };
   Layout lo{};
   size_t o = 0;
@@ -284,6 +285,7 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int
   w.lz_ab = (double *)(b + lo.off[i++]);
   w.SK = b + lo.off[i++];
   w.sk_bytes = kTailScratch;
+  w.hh = b + lo.off[i++];
   // pinned host mirrors, grown on demand
   const int lz_cols = std::max(lz_steps, 1) * std::max(lz_nvec, 1);
   if (L > h_cap_L || lz_cols > h_cap_lz) {
@@ -476,22 +478,112 @@ static void rocsolver_check(rocblas_status st, const char *what) {
   }
 }
 
-static void householder(Ctx &c, bool cplx, void *X, int64_t ld, int64_t N, int L) {
-  if (cplx) {
-    rocsolver_check(rocsolver_zgeqrf(c.rb, (rocblas_int)N, L, (rocblas_double_complex *)X,
-                                     (rocblas_int)ld, (rocblas_double_complex *)c.w.tau),
-                    "rocsolver_zgeqrf");
-    rocsolver_check(rocsolver_zungqr(c.rb, (rocblas_int)N, L, L, (rocblas_double_complex *)X,
-                                     (rocblas_int)ld, (rocblas_double_complex *)c.w.tau),
-                    "rocsolver_zungqr");
-  } else {
-    rocsolver_check(rocsolver_dgeqrf(c.rb, (rocblas_int)N, L, (double *)X, (rocblas_int)ld,
-                                     (double *)c.w.tau),
-                    "rocsolver_dgeqrf");
-    rocsolver_check(rocsolver_dorgqr(c.rb, (rocblas_int)N, L, L, (double *)X, (rocblas_int)ld,
-                                     (double *)c.w.tau),
-                    "rocsolver_dorgqr");
+// Split count of a K-split product with `tiles` output tiles over K rows.
+static int ksplits(int64_t K, int tiles) {
+  int s = (1024 + tiles - 1) / tiles;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, K / 256));
+  return std::max(1, std::min(s, 32));
+}
+
+// C (Mp x n) <- (I - V op(T) V^H) C with op(T) = T^H (trans) or T: the block
+// reflector of one panel (V: Mp x nbp with explicit unit diagonal; T: nbp x
+// nbp, leading dimension nbp).  W = V^H C goes through K-split partials in P
+// and lands in Ri, op(T) W in A.
+static void apply_block_reflector(Ctx &c, bool cplx, const void *V, int64_t ldv, int64_t Mp,
+                                  int nbp, const void *T, bool trans, void *C, int64_t ldc,
+                                  int n) {
+  Work &w = c.w;
+  const int64_t cap = (int64_t)w.nsplit * w.L * w.L / ((int64_t)nbp * n);
+  const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(ksplits(Mp, (n + 63) / 64), cap));
+  const int bk = gemm_bk();
+  {
+    GemmArgs a = gargs();
+    a.A = V; a.lda = ldv;
+    a.B = C; a.ldb = ldc;
+    a.M = nbp; a.N = n; a.K = (int)Mp;
+    a.k_per_split = (int)(((Mp + ns - 1) / ns + bk - 1) / bk * bk);
+    a.C = w.P; a.ldc = nbp; a.split_stride = (int64_t)nbp * n;
+    gemm(cplx, false, true, false, false, GEMM_SMALL, a, ns, c.stream);
+    sum_splits(cplx, w.P, ns, (int64_t)nbp * n, nbp, nbp, n, w.Ri, nbp, c.stream);
   }
+  {
+    GemmArgs a = gargs();
+    a.A = T; a.lda = nbp;
+    a.B = w.Ri; a.ldb = nbp;
+    a.M = nbp; a.N = n; a.K = nbp;
+    a.C = w.A; a.ldc = nbp;
+    gemm(cplx, false, trans, false, false, GEMM_SMALL, a, 1, c.stream);
+  }
+  {
+    GemmArgs a = bigargs(c);
+    a.A = V; a.lda = ldv;
+    a.B = w.A; a.ldb = nbp;
+    a.M = (int)Mp; a.N = n; a.K = nbp;
+    a.C = C; a.ldc = ldc;
+    a.alpha = -1.0; a.beta = 1.0;
+    gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);
+  }
+}
+
+// Width of the block reflectors of the Householder QR (a multiple of the
+// column-step panel width, at most kHhMaxOuter).
+#ifndef CHASE_HH_OUTER
+#define CHASE_HH_OUTER 128
+#endif
+
+// Blocked Householder QR of X (N x L) in the geqrf convention, then the
+// explicit Q (the first L columns of H_0 ... H_{L-1}) in X, as orgqr/ungqr
+// form it.  Two levels of blocking: column steps (hh_column) factor panels
+// of nbi columns, whose block reflectors update the rest of their outer
+// panel of nbo columns; the outer panel's block reflector (its compact WY
+// factor T from V^H V) then updates the trailing columns, where the
+// products are wide enough for the MFMA tiles.  Q is accumulated from the
+// identity with the outer block reflectors, last panel first.  V (N x L,
+// leading dimension ld) receives the reflector vectors; the outer T of
+// panel p sits at G + p nbo^2; tau in w.tau.
+static void householder(Ctx &c, bool cplx, void *X, void *V, int64_t ld, int64_t N, int L) {
+  if (L <= 0) return;
+  Work &w = c.w;
+  const size_t es = cplx ? 16 : 8;
+  // widths <= L / 2 keep the T store (ceil(L / nbo) nbo^2) and W (nbo x L)
+  // within the L x L buffers
+  const int nbi = std::max(1, std::min(kHhNB, L / 2));
+  const int nbo = std::max(nbi, std::min(CHASE_HH_OUTER, L / 2) / nbi * nbi);
+  const int np = (L + nbo - 1) / nbo;
+  auto at = [&](void *B, int64_t r, int64_t col) { return (char *)B + es * (r + col * ld); };
+  auto tstore = [&](int p) { return (char *)w.G + es * (size_t)p * nbo * nbo; };
+  fill_zero(cplx, V, ld, (int)N, L, c.stream);
+  fill_zero(false, w.flag, 1, 1, 1, c.stream);  // the Gram's skip flag
+  for (int p = 0; p < np; ++p) {
+    const int j0 = p * nbo, nbop = std::min(nbo, L - j0);
+    for (int jq = j0; jq < j0 + nbop; jq += nbi) {
+      const int nbq = std::min(nbi, j0 + nbop - jq);
+      const int64_t Mq = N - jq;
+      void *Vq = at(V, jq, jq);
+      void *tq = (char *)w.tau + es * jq;
+      for (int jj = 0; jj <= nbq; ++jj)
+        hh_column(cplx, at(X, jq, jq), ld, (int)Mq, nbq, jj, Vq, ld, tq, w.hh, c.stream);
+      const int rest = j0 + nbop - jq - nbq;
+      if (rest > 0) {
+        gram(c, cplx, Vq, ld, Mq, nbq, w.T, 0);  // S = V^H V
+        hh_larft(cplx, w.T, nbq, tq, w.R, nbq, nbq, c.stream);
+        apply_block_reflector(c, cplx, Vq, ld, Mq, nbq, w.R, true, at(X, jq, jq + nbq), ld, rest);
+      }
+    }
+    const int nt = L - j0 - nbop;
+    gram(c, cplx, at(V, j0, j0), ld, N - j0, nbop, w.T, 0);
+    hh_larft(cplx, w.T, nbop, (char *)w.tau + es * j0, tstore(p), nbop, nbop, c.stream);
+    if (nt > 0)
+      apply_block_reflector(c, cplx, at(V, j0, j0), ld, N - j0, nbop, tstore(p), true,
+                            at(X, j0, j0 + nbop), ld, nt);
+  }
+  set_identity(cplx, X, ld, (int)N, L, c.stream);
+  for (int p = np - 1; p >= 0; --p) {
+    const int j0 = p * nbo, nbop = std::min(nbo, L - j0);
+    apply_block_reflector(c, cplx, at(V, j0, j0), ld, N - j0, nbop, tstore(p), false,
+                          at(X, j0, j0), ld, L - j0);
+  }
+  CHASE_HIP(hipGetLastError());
 }
 
 // Alg. 3 for one variant.  The passes of CholeskyQR (Alg. 2) alternate
@@ -502,7 +594,7 @@ QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, c
          int inject) {
   Work &w = c.w;
   if (variant == CHASE_QR_HOUSEHOLDER) {
-    householder(c, cplx, X, ld, N, L);
+    householder(c, cplx, X, Xalt, ld, N, L);
     return {X, false, CHASE_QR_HOUSEHOLDER};
   }
   int npass = variant == CHASE_QR_CHOL1 ? 1 : variant == CHASE_QR_CHOL2 ? 2 : 3;
@@ -525,7 +617,7 @@ QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, c
   CHASE_HIP(hipStreamSynchronize(c.stream));
   if (w.h_flag[0] != 0) {
     const int fp = std::min(std::max(w.h_flag[1], 0), npass - 1);
-    householder(c, cplx, inputs[fp], ld, N, L);
+    householder(c, cplx, inputs[fp], inputs[fp] == X ? Xalt : X, ld, N, L);
     return {inputs[fp], true, CHASE_QR_HOUSEHOLDER};
   }
   return {in, false, variant};

@@ -27,6 +27,7 @@ struct Work {
   void *LV = nullptr, *LW = nullptr, *Lh = nullptr, *LhP = nullptr;  // Lanczos runs
   double *lz_ab = nullptr;
   void *SK = nullptr;                                   // remainder-split partials
+  void *hh = nullptr;                                   // Householder QR state
   size_t sk_bytes = 0;
   // pinned host mirrors
   double *h_theta = nullptr, *h_resid = nullptr, *h_ab = nullptr;

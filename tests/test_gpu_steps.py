@@ -134,6 +134,49 @@ def test_qr_fallback_to_householder(P, gpu, cplx):
         assert np.linalg.norm(Q.conj().T @ Q - np.eye(L)) <= 100 * L * U64
 
 
+HH_SHAPES = [
+    # N, L, cplx: one column, two one-column panels, N == L, ragged panels,
+    # several row blocks of the column kernel, and a narrow first-row panel
+    (300, 1, False), (257, 2, True), (64, 64, False), (96, 96, True), (257, 33, True),
+    (1100, 97, False), (5000, 200, True), (70000, 40, False),
+]
+
+
+@pytest.mark.parametrize("N,L,cplx", HH_SHAPES)
+def test_householder_matches_lapack_convention(P, gpu, N, L, cplx):
+    """The blocked Householder QR follows geqrf/orgqr's convention (beta =
+    -sign(Re alpha) ||x||, real R diagonal), so its Q equals numpy's
+    (LAPACK) Q column by column to rounding, with no phase alignment; two
+    runs on the same input are bit-identical (fixed-order reductions)."""
+    print("householder case", N, L, cplx, flush=True)
+    X = planted_block(N, L, 1e6, 31, cplx)
+    Qref = oqr.householder_qr(X)
+    Xd = to_dev(X, gpu)
+    assert not P.chase_qr_factor(Xd, "householder")
+    Q = to_host(Xd)
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(L)) <= 100 * L * U64
+    assert col_rel_err(Q, Qref) <= 100 * L * 1e6 * U64
+    Xd2 = to_dev(X, gpu)
+    P.chase_qr_factor(Xd2, "householder")
+    assert np.array_equal(to_host(Xd2), Q)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_householder_rank_deficient(P, gpu, cplx):
+    """Zero and repeated columns: the reflector of a zero column is the
+    identity (tau = 0); Q stays orthonormal and spans X."""
+    N, L = 500, 70
+    X = planted_block(N, L, 10.0, 32, cplx)
+    X[:, 5] = 0
+    X[:, 40] = X[:, 3]
+    X[:, 41] = 2 * X[:, 40] - X[:, 7]
+    Xd = to_dev(np.asfortranarray(X), gpu)
+    P.chase_qr_factor(Xd, "householder")
+    Q = to_host(Xd)
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(L)) <= 100 * L * U64
+    assert np.linalg.norm(X - Q @ (Q.conj().T @ X)) <= 1e-13 * np.linalg.norm(X)
+
+
 @pytest.mark.parametrize("N,L,cplx", [(1000, 60, False), (600, 37, True), (200, 130, False)])
 def test_rayleigh_ritz_and_residuals(P, gpu, N, L, cplx):
     H, lam = synth.planted_numpy(N, "uniform", 13, cplx)
