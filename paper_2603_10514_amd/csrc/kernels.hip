@@ -21,6 +21,7 @@ template <> struct Num<double> {
   __device__ static double scale(double a, double s) { return a * s; }
   // a + (the value of lane ^ m)
   __device__ static double add_xor(double a, int m) { return a + __shfl_xor(a, m); }
+  __device__ static double sel(bool p, double a, double b) { return p ? a : b; }
 };
 template <> struct Num<double2> {
   __device__ static double2 zero() { return make_double2(0.0, 0.0); }
@@ -35,6 +36,10 @@ template <> struct Num<double2> {
   __device__ static double2 scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
   __device__ static double2 add_xor(double2 a, int m) {
     return make_double2(a.x + __shfl_xor(a.x, m), a.y + __shfl_xor(a.y, m));
+  }
+  // p ? a : b by components (a select of the vector struct goes through memory)
+  __device__ static double2 sel(bool p, double2 a, double2 b) {
+    return make_double2(p ? a.x : b.x, p ? a.y : b.y);
   }
 };
 __device__ __forceinline__ double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -97,66 +102,99 @@ __global__ __launch_bounds__(256) void k_trace_shift(E *G, int64_t ldg, int n, d
 // One work-group factors the b x b (b <= 64) diagonal block of G at (p0, p0)
 // from its upper triangle (G = R^H R, right-looking), writes R and R^{-1}
 // (upper, zero below the diagonal) and reports a non-positive or non-finite
-// pivot through flag.
+// pivot through flag.  Thread (c, part) = (t / 4, t % 4) keeps the entries
+// of column c in rows part, part + 4, ... in registers.  Step j of the
+// factorisation: the owners publish row j (unscaled) in LDS, one barrier,
+// and every thread scales it by 1 / sqrt(pivot) on the fly and updates its
+// entries below row j.  The inverse runs bottom-up by rows,
+// X[i][c] = (delta_ic - sum_{q > i} R[i][q] X[q][c]) / R[i][i], each sum
+// split over the four threads of column c and combined by shuffles, with R
+// read from LDS and X kept in registers: no barrier per row.
 template <typename E>
 __global__ __launch_bounds__(256) void k_chol_diag(const E *G, int64_t ldg, E *R, int64_t ldr,
                                                    E *Ri, int64_t ldi, int p0, int b, int *flag,
                                                    int pass, int inject) {
-  __shared__ E L[64][65];
-  __shared__ E X[64][65];
+  __shared__ E sR[64][65];
+  __shared__ E srow[2][64];
   if (flag[0] != 0) return;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, c = t >> 2, part = t & 3;
   if (inject) {
     if (t == 0) { flag[0] = p0 + 1; flag[1] = pass; }
     return;
   }
-  for (int idx = t; idx < b * b; idx += 256) {
-    const int r = idx % b, c = idx / b;
-    L[r][c] = (r <= c) ? G[(int64_t)(p0 + c) * ldg + p0 + r] : Num<E>::zero();
+  const bool col = c < b;
+  const int cc = min(c, b - 1);
+  E a[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {  // unconditional loads from inside the block, then masked
+    const int i = part + 4 * k;
+    const E g = G[(int64_t)(p0 + cc) * ldg + p0 + min(i, b - 1)];
+    a[k] = Num<E>::sel(col && i <= c, g, Num<E>::zero());
   }
-  __syncthreads();
+#pragma unroll 1
   for (int j = 0; j < b; ++j) {
-    const double d = Num<E>::re(L[j][j]);
+    E *rowb = srow[j & 1];
+    if (part == (j & 3) && col) {
+      E v = Num<E>::zero();
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (k == (j >> 2)) v = a[k];
+      rowb[c] = v;
+    }
+    __syncthreads();
+    const double d = Num<E>::re(rowb[j]);
     if (!(d > 0.0) || !isfinite(d)) {
       if (t == 0) { flag[0] = p0 + j + 1; flag[1] = pass; }
       return;
     }
     const double rj = sqrt(d), inv = 1.0 / rj;
-    __syncthreads();
-    for (int c = j + 1 + t; c < b; c += 256) L[j][c] = Num<E>::scale(L[j][c], inv);
-    if (t == 0) L[j][j] = Num<E>::real(rj);
-    __syncthreads();
-    for (int idx = t; idx < b * b; idx += 256) {
-      const int i = idx % b, c = idx / b;
-      if (i > j && i <= c) L[i][c] = L[i][c] - Num<E>::mul(Num<E>::cj(L[j][i]), L[j][c]);
+    const E ujc = Num<E>::scale(rowb[cc], inv);
+    E rv[16];  // row j at this thread's rows, all reads issued together
+#pragma unroll
+    for (int k = 0; k < 16; ++k) rv[k] = rowb[min(part + 4 * k, b - 1)];
+    const E own = Num<E>::sel(c > j, ujc, Num<E>::real(rj));  // the new entry in row j
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {  // selects, no branches
+      const int i = part + 4 * k;
+      const E upd = a[k] - Num<E>::mul(Num<E>::cj(Num<E>::scale(rv[k], inv)), ujc);
+      const E keep = Num<E>::sel(i > j && i <= c && col, upd, a[k]);
+      a[k] = Num<E>::sel(i == j && c >= j, own, keep);
     }
-    __syncthreads();
   }
-  // R^{-1} by back substitution, one row at a time from the bottom:
-  // X[i][c] = (delta_ic - sum_{q = i+1..c} R[i][q] X[q][c]) / R[i][i].  Four
-  // threads per column split each sum (every fourth q), combined by shuffles
-  // within the four consecutive lanes, so all 256 threads work on every row.
-  for (int idx = t; idx < 64 * 64; idx += 256) X[idx % 64][idx / 64] = Num<E>::zero();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) sR[part + 4 * k][c] = a[k];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int i = part + 4 * k;
+    if (col && i < b) R[(int64_t)(p0 + c) * ldr + p0 + i] = a[k];
+  }
   __syncthreads();
-  {
-    const int c = t >> 2, part = t & 3;
-    for (int i = b - 1; i >= 0; --i) {
-      E s = Num<E>::zero();
-      if (c < b && c > i)
-        for (int q = i + 1 + part; q <= c; q += 4) s = s + Num<E>::mul(L[i][q], X[q][c]);
-      s = Num<E>::add_xor(s, 1);
-      s = Num<E>::add_xor(s, 2);
-      if (part == 0 && c < b && c >= i) {
-        const double inv = 1.0 / Num<E>::re(L[i][i]);
-        X[i][c] = c == i ? Num<E>::real(inv) : Num<E>::scale(-s, inv);
-      }
-      __syncthreads();
+  E x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = Num<E>::zero();
+#pragma unroll 1
+  for (int i = b - 1; i >= 0; --i) {
+    E rv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) rv[k] = sR[i][part + 4 * k];
+    E s = Num<E>::zero();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const E term = Num<E>::mul(rv[k], x[k]);
+      s = Num<E>::sel(part + 4 * k > i, s + term, s);
     }
+    s = Num<E>::add_xor(s, 1);
+    s = Num<E>::add_xor(s, 2);
+    const double inv = 1.0 / Num<E>::re(sR[i][i]);
+    const E v = Num<E>::sel(c == i, Num<E>::real(inv), Num<E>::scale(-s, inv));
+    const bool own = part == (i & 3) && col && c >= i;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = Num<E>::sel(own && k == (i >> 2), v, x[k]);
   }
-  for (int idx = t; idx < b * b; idx += 256) {
-    const int r = idx % b, c = idx / b;
-    R[(int64_t)(p0 + c) * ldr + p0 + r] = (r <= c) ? L[r][c] : Num<E>::zero();
-    Ri[(int64_t)(p0 + c) * ldi + p0 + r] = X[r][c];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int i = part + 4 * k;
+    if (col && i < b) Ri[(int64_t)(p0 + c) * ldi + p0 + i] = x[k];
   }
 }
 

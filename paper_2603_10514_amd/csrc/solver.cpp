@@ -380,6 +380,11 @@ int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, v
   return launches;
 }
 
+// Tile shape of the K-split products X^H Y (Gram matrices, V^H C).
+#ifndef CHASE_GRAM_SHAPE
+#define CHASE_GRAM_SHAPE GEMM_BIG
+#endif
+
 // G = X^H X (upper triangle by tiles, deterministic split-K) -> Hermitian G.
 static void gram(Ctx &c, bool cplx, const void *X, int64_t ldx, int64_t N, int L, void *G,
                  int average_with_B, const void *B = nullptr, int64_t ldB = 0) {
@@ -396,7 +401,7 @@ static void gram(Ctx &c, bool cplx, const void *X, int64_t ldx, int64_t N, int L
   a.k_per_split = (int)(((N + ns - 1) / ns + bk - 1) / bk * bk);
   a.C = w.P; a.ldc = L; a.split_stride = (int64_t)L * L;
   a.flag = average_with_B ? nullptr : w.flag;
-  gemm(cplx, false, true, false, false, GEMM_SMALL, a, ns, c.stream);
+  gemm(cplx, false, true, false, false, CHASE_GRAM_SHAPE, a, ns, c.stream);
   reduce_hermitian(cplx, w.P, ns, (int64_t)L * L, L, L, G, L, average_with_B, c.stream);
 }
 
@@ -503,7 +508,7 @@ static void apply_block_reflector(Ctx &c, bool cplx, const void *V, int64_t ldv,
     a.M = nbp; a.N = n; a.K = (int)Mp;
     a.k_per_split = (int)(((Mp + ns - 1) / ns + bk - 1) / bk * bk);
     a.C = w.P; a.ldc = nbp; a.split_stride = (int64_t)nbp * n;
-    gemm(cplx, false, true, false, false, GEMM_SMALL, a, ns, c.stream);
+    gemm(cplx, false, true, false, false, CHASE_GRAM_SHAPE, a, ns, c.stream);
     sum_splits(cplx, w.P, ns, (int64_t)nbp * n, nbp, nbp, n, w.Ri, nbp, c.stream);
   }
   {
