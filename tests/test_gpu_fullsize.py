@@ -140,3 +140,25 @@ def test_filter_64bit_indexing(gpu, cplx, prec):
     err = col_rel_err(out[:, cols], ref)
     tol = (8.0 * maxdeg * np.sqrt(N) * U32) if prec else (4.0 * maxdeg * N * U64)
     assert err <= tol, (err, tol)
+
+
+def test_householder_full_size(gpu):
+    """The Householder QR (the Alg. 3 fallback) on a block of the bench
+    workload's shape, 20000 x 1300 complex: Q equals LAPACK's column by
+    column (same sign convention), is orthonormal, and a rerun on the same
+    input is bit-identical."""
+    import torch
+    import paper_2603_10514_amd as P
+    L = NEV + NEX
+    print("householder full size", N, L, flush=True)
+    X = synth.start_block(N, L, 41, True)
+    Qref = np.linalg.qr(X, mode="reduced")[0]
+    Xd = to_dev(X, gpu)
+    assert not P.chase_qr_factor(Xd, "householder")
+    orth = torch.linalg.norm(Xd.conj().T.contiguous() @ Xd - torch.eye(L, dtype=Xd.dtype, device=Xd.device))
+    assert float(orth) <= 100 * L * U64
+    Q = to_host(Xd)
+    assert col_rel_err(Q, Qref) <= 100 * L * 10 * U64
+    Xd2 = to_dev(X, gpu)
+    P.chase_qr_factor(Xd2, "householder")
+    assert torch.equal(Xd2, Xd)
