@@ -194,7 +194,9 @@ void chase_handle_destroy(chase_handle *h);
 
 /* ------------------------------------------------------ step entry points --
  * Each runs one step of the hot path on device buffers, for testing the
- * steps one by one against a reference.  Workspace is allocated per call. */
+ * steps one by one against a reference.  Workspace is allocated per call.
+ * The calls that take a dtype (and chase_filter its precision) return
+ * CHASE_EINVAL for a value outside the enum before touching any buffer. */
 
 /* Chebyshev filter with per-vector degrees (Alg. 4, Sec. 2.2): column a of
  * out = p_{m_a}(H) V[:, a], p_m(x) = C_m((x-c)/e) / C_m((gamma-c)/e).

@@ -228,10 +228,15 @@ void chase_handle_destroy(chase_handle *h) {
 }
 
 // ------------------------------------------------------------ step calls --
+static bool dtype_ok(chase_dtype d) { return d == CHASE_REAL64 || d == CHASE_COMPLEX128; }
+
 chase_status chase_filter(chase_dtype dtype, chase_precision prec, const void *H, int64_t N,
                           int64_t ldh, const void *V, int64_t ldv, int32_t ncols,
                           const int32_t *deg, double c, double e, double gamma, void *out,
                           int64_t ldo, void *stream) {
+  if (!dtype_ok(dtype)) return fail(CHASE_EINVAL, "unknown dtype");
+  if (prec != CHASE_PREC_FP64 && prec != CHASE_PREC_MIXED)
+    return fail(CHASE_EINVAL, "unknown precision");
   if (N < 1 || ncols < 0 || ncols > N || ldh < N || ldv < N || ldo < N)
     return fail(CHASE_EINVAL, "invalid sizes");
   if (ncols == 0) return CHASE_OK;  // nothing is read or written
@@ -281,6 +286,7 @@ void chase_degrees(const double *theta, const double *resid, int32_t ncols, doub
 
 chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx, int32_t ncols,
                              chase_qr variant, int32_t *chol_failed, void *stream) {
+  if (!dtype_ok(dtype)) return fail(CHASE_EINVAL, "unknown dtype");
   if (!X) return fail(CHASE_EINVAL, "X is NULL");
   if (N < 1 || ncols < 1 || ncols > N || ldx < N) return fail(CHASE_EINVAL, "invalid sizes");
   if (variant < CHASE_QR_CHOL1 || variant > CHASE_QR_HOUSEHOLDER)
@@ -311,6 +317,7 @@ chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx,
 chase_status chase_rayleigh_ritz(chase_dtype dtype, const void *H, int64_t N, int64_t ldh,
                                  const void *Q, int64_t ldq, int32_t ncols, double *ritz, void *V,
                                  int64_t ldv, void *HV, int64_t ldhv, void *stream) {
+  if (!dtype_ok(dtype)) return fail(CHASE_EINVAL, "unknown dtype");
   if (!H || !Q || !ritz || !V || !HV) return fail(CHASE_EINVAL, "NULL argument");
   if (N < 1 || ncols < 1 || ncols > N || ldh < N || ldq < N || ldv < N || ldhv < N)
     return fail(CHASE_EINVAL, "invalid sizes");
@@ -338,6 +345,7 @@ chase_status chase_rayleigh_ritz(chase_dtype dtype, const void *H, int64_t N, in
 chase_status chase_residuals(chase_dtype dtype, const void *HV, int64_t ldhv, const void *V,
                              int64_t ldv, int64_t N, int32_t ncols, const double *ritz,
                              double *resid, void *stream) {
+  if (!dtype_ok(dtype)) return fail(CHASE_EINVAL, "unknown dtype");
   if (!HV || !V || !ritz || !resid) return fail(CHASE_EINVAL, "NULL argument");
   if (N < 1 || ncols < 1 || ldhv < N || ldv < N) return fail(CHASE_EINVAL, "invalid sizes");
   return guarded([&] {
@@ -356,6 +364,7 @@ chase_status chase_residuals(chase_dtype dtype, const void *HV, int64_t ldhv, co
 chase_status chase_lanczos(chase_dtype dtype, const void *H, int64_t N, int64_t ldh,
                            const void *V0, int32_t nvec, int32_t steps, int32_t nsearch,
                            double *alpha, double *beta, double *bounds, void *stream) {
+  if (!dtype_ok(dtype)) return fail(CHASE_EINVAL, "unknown dtype");
   if (!H || !V0 || !alpha || !beta || !bounds) return fail(CHASE_EINVAL, "NULL argument");
   if (N < 1 || ldh < N || steps < 1 || nsearch < 1 || nsearch > N)
     return fail(CHASE_EINVAL, "invalid sizes");

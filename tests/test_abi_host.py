@@ -163,3 +163,30 @@ def test_invalid_arguments_rejected_without_gpu(pkg):
             st = pkg.lib.chase_lanczos_bounds(ab.ctypes.data_as(pkg._dp), ab.ctypes.data_as(pkg._dp),
                                               nv, 4, 10, nsearch, bd.ctypes.data_as(pkg._dp))
             assert st == pkg.CHASE_EINVAL
+
+
+def test_step_calls_reject_unknown_dtype_without_gpu(pkg):
+    """Every step call that takes a dtype (and the filter its precision)
+    rejects a value outside the enum before any buffer is touched."""
+    p = ctypes.c_void_p(16)  # never dereferenced
+    d = np.zeros(8)
+    deg = np.ones(2, dtype=np.int32)
+    dp = d.ctypes.data_as(pkg._dp)
+    fl = ctypes.c_int32(0)
+    calls = {
+        "filter": lambda dt, pr=pkg.PREC_FP64: pkg.lib.chase_filter(
+            dt, pr, p, 10, 10, p, 10, 2, deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            0.0, 1.0, -2.0, p, 10, None),
+        "qr": lambda dt: pkg.lib.chase_qr_factor(dt, p, 10, 10, 2, 2, ctypes.byref(fl), None),
+        "rr": lambda dt: pkg.lib.chase_rayleigh_ritz(dt, p, 10, 10, p, 10, 2, dp, p, 10, p, 10,
+                                                     None),
+        "resid": lambda dt: pkg.lib.chase_residuals(dt, p, 10, p, 10, 10, 2, dp, dp, None),
+        "lanczos": lambda dt: pkg.lib.chase_lanczos(dt, p, 10, 10, p, 1, 4, 2, dp, dp, dp, None),
+    }
+    for name, call in calls.items():
+        for bad in (2, -1, 7):
+            assert call(bad) == pkg.CHASE_EINVAL, (name, bad)
+            assert b"dtype" in pkg.lib.chase_last_error()
+    for bad in (2, -1):
+        assert calls["filter"](pkg.REAL64, bad) == pkg.CHASE_EINVAL
+        assert b"precision" in pkg.lib.chase_last_error()
