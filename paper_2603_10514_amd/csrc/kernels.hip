@@ -428,7 +428,8 @@ template <> __device__ __forceinline__ double2 recip(double2 a) {
 //    P[r, c] (c = jj..nbp-1) and, from the block holding row jj, that row.
 // Nothing waits on another block: the launch boundary orders the steps.
 // Each wave reduces its NB accumulators by a halving exchange that leaves
-// accumulator `lane` in lane `lane` (63 exchanges instead of 6 per value).
+// accumulator `lane` in lane `lane`: 63 exchanges in all for 64 values,
+// against 6 per value for a butterfly sum of each.
 template <typename E, int NB>
 __global__ __launch_bounds__(256) void k_hh_column(E *__restrict__ P, int64_t ld, int Mp, int nbp,
                                                    int jj, int nprev, E *__restrict__ Vb,
