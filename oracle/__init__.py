@@ -21,7 +21,9 @@ Parity status per module (the pins live in ``tests/test_oracle_*.py``):
   chebyshev  pinned (closed forms of the Chebyshev polynomials, Sec. 2.1)
   filter     pinned (spectral closed form of p(A)V on planted spectra, Sec. 2.3)
   estimate   pinned (hand-evaluated cases; reduction of estimate (1.2) to
-             estimate (1.1) at k = 0; empirical upper-bound property, Sec. 4.3)
+             estimate (1.1) at k = 0; empirical upper-bound property, Sec. 4.3;
+             Lemma 3.1's closed form on filtered eigenvectors; Theorem 3.4
+             by brute force)
   qr         pinned (orthogonality and backward error on planted singular
              values; Table 1 validity ranges; LAPACK Householder QR)
   rr         pinned (full diagonalisation of planted spectra)

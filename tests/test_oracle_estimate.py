@@ -78,3 +78,50 @@ def test_estimate_bounds_exact_condition_number(deg_opt):
     assert r.converged == nev
     for rec in r.log:
         assert rec["cond_est"] >= rec["cond_exact"], rec
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_deflation_theorem_brute_force(cplx):
+    """Theorem 3.4 (Sec. 3.3), the step that lets the locked block drop out
+    of the estimate: for A (n x q) and B (n x p) with A^H B = 0,
+    kappa_2([A B]) <= (sigma_1(A) + sigma_1(B)) / min(sigma_q(A), sigma_p(B)).
+    Checked on random pairs with spread singular values, including pairs
+    where the bound is nearly tight (one singular value per block)."""
+    rng = np.random.default_rng(41)
+    for trial in range(200):
+        n = int(rng.integers(8, 60))
+        q = int(rng.integers(1, n // 2))
+        p = int(rng.integers(1, n - q))
+        G = rng.standard_normal((n, q + p)) + (1j * rng.standard_normal((n, q + p)) if cplx else 0)
+        U = np.linalg.qr(G)[0]
+        sa = 10.0 ** rng.uniform(-4, 4, q)
+        sb = 10.0 ** rng.uniform(-4, 4, p)
+        Wa = np.linalg.qr(rng.standard_normal((q, q)))[0]
+        Wb = np.linalg.qr(rng.standard_normal((p, p)))[0]
+        A = (U[:, :q] * sa) @ Wa
+        B = (U[:, q:] * sb) @ Wb
+        assert np.linalg.norm(A.conj().T @ B) <= 1e-10 * np.linalg.norm(A) * np.linalg.norm(B)
+        s = np.linalg.svd(np.hstack([A, B]), compute_uv=False)
+        bound = (sa.max() + sb.max()) / min(sa.min(), sb.min())
+        assert s[0] / s[-1] <= bound * (1 + 1e-9), (trial, s[0] / s[-1], bound)
+
+
+@pytest.mark.parametrize("m", [1, 5, 20])
+def test_filtered_eigenvectors_condition_closed_form(m):
+    """Lemma 3.1, statement 1 (Sec. 3.1): filtering the wanted eigenvectors
+    themselves gives kappa_2 = |C_m(t_1)| / |C_m(t_l)| with t = (lambda - c)/e,
+    computed here by SVD of the oracle's filtered block and by cosh/arccosh;
+    it never exceeds estimate (1.1) = |rho(lambda_1)|^m."""
+    N, L = 300, 24
+    lam = np.sort(np.concatenate([np.linspace(-2.0, -1.2, L), np.linspace(-1.0, 5.0, N - L)]))
+    H = np.diag(lam)
+    c, e = 0.5 * (-1.0 + 5.0), 0.5 * (5.0 + 1.0)
+    from oracle import filter as ofilter
+    X = np.eye(N)[:, :L]
+    Y = ofilter.chebyshev_filter(H, X, np.full(L, m), c, e, lam[0])
+    s = np.linalg.svd(Y, compute_uv=False)
+    t = (lam[:L] - c) / e
+    cm = np.cosh(m * np.arccosh(np.abs(t)))  # |C_m(t)| for |t| >= 1
+    closed = cm.max() / cm.min()
+    assert s[0] / s[-1] == pytest.approx(closed, rel=1e-10)
+    assert closed <= est.cond_estimate(lam[0], m, m, lam[0], c, e) * (1 + 1e-12)
