@@ -379,6 +379,108 @@ __global__ __launch_bounds__(256) void k_norm_scale_cols(const E *w, int64_t ldw
   if (threadIdx.x == 0) beta[blockIdx.x] = s;
 }
 
+// Block sums of D doubles per thread over 256 threads (D a power of two up
+// to 64), in a fixed order: a halving exchange leaves partial sum `lane` in
+// lane `lane` of each wave, then the four waves are added in wave order.
+// Returns with out[0..D) filled (LDS) and the block synchronised.
+template <int D, int M>
+__device__ __forceinline__ void fold_lanes(double (&acc)[D]) {
+  if constexpr (M >= D) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[i] += __shfl_xor(acc[i], M);
+    fold_lanes<D, M / 2>(acc);
+  }
+}
+template <int D, int H>
+__device__ __forceinline__ void halve_lanes(double (&acc)[D], int lane) {
+  if constexpr (H >= 1) {
+    const bool up = (lane & H) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double send = up ? acc[i] : acc[i + H];
+      const double keep = up ? acc[i + H] : acc[i];
+      acc[i] = keep + __shfl_xor(send, H);
+    }
+    halve_lanes<D, H / 2>(acc, lane);
+  }
+}
+template <int D>
+__device__ __forceinline__ void block_sums(double (&acc)[D], double (*s_red)[64], double *out) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  fold_lanes<D, 32>(acc);
+  halve_lanes<D, D / 2>(acc, lane);
+  __syncthreads();
+  s_red[wave][lane] = acc[0];
+  __syncthreads();
+  if (t < D) out[t] = s_red[0][t] + s_red[1][t] + s_red[2][t] + s_red[3][t];
+  __syncthreads();
+}
+
+// One Lanczos step after the product w = H v_j, for orders small enough that
+// one work-group per run can stream the run's whole basis (there the
+// solver's form with several wide launches per step is latency-bound):
+// alpha_j = Re(v_j^H w), two passes of
+// classical Gram-Schmidt against the run's basis v_0..v_j (h = V^H w, then
+// w -= V h), beta_j = ||w||, v_{j+1} = w / beta_j.  The same steps and the
+// same layout as the wide form: run r's basis vector i is column
+// i nv + r of LV; alpha at ab[j nv + r], beta at ab[(k + j) nv + r].
+template <typename E>
+__global__ __launch_bounds__(256) void k_lz_step_small(E *LV, int64_t ldv, int N, int j, int nv,
+                                                       E *W, int64_t ldw, double *ab, int k) {
+  constexpr int ES = sizeof(E) / sizeof(double), CH = 16, D = CH * ES;
+  __shared__ double s_red[4][64];
+  __shared__ double s_out[64];
+  __shared__ double sh[256];
+  __shared__ E s_h[kLzSmallMaxBasis];
+  const int r = blockIdx.x, t = threadIdx.x;
+  const int nb = j + 1;
+  E *w = W + (int64_t)r * ldw;
+  auto vcol = [&](int i) { return LV + ((int64_t)i * nv + r) * ldv; };
+  {
+    const E *vj = vcol(j);
+    double s = 0.0;
+    for (int n = t; n < N; n += 256)
+      s += Num<E>::re(vj[n]) * Num<E>::re(w[n]) + Num<E>::im(vj[n]) * Num<E>::im(w[n]);
+    s = block_sum256(s, sh);
+    if (t == 0) ab[(int64_t)j * nv + r] = s;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i0 = 0; i0 < nb; i0 += CH) {
+      double acc[D];
+#pragma unroll
+      for (int u = 0; u < D; ++u) acc[u] = 0.0;
+      for (int n = t; n < N; n += 256) {
+        const E wn = w[n];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const E y = Num<E>::mul(Num<E>::cj(vcol(min(i0 + u, nb - 1))[n]), wn);
+          acc[ES * u] += Num<E>::re(y);
+          if constexpr (ES == 2) acc[ES * u + 1] += Num<E>::im(y);
+        }
+      }
+      block_sums<D>(acc, s_red, s_out);
+      if (t < CH && i0 + t < nb) {
+        if constexpr (ES == 2) s_h[i0 + t] = make_double2(s_out[2 * t], s_out[2 * t + 1]);
+        else s_h[i0 + t] = s_out[t];
+      }
+      __syncthreads();
+    }
+    for (int n = t; n < N; n += 256) {
+      E x = w[n];
+      for (int i = 0; i < nb; ++i) x = x - Num<E>::mul(vcol(i)[n], s_h[i]);
+      w[n] = x;
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+  for (int n = t; n < N; n += 256) s += Num<E>::abs2(w[n]);
+  s = sqrt(block_sum256(s, sh));
+  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  E *vn = vcol(j + 1);
+  for (int n = t; n < N; n += 256) vn[n] = Num<E>::scale(w[n], inv);
+  if (t == 0) ab[(int64_t)(k + j) * nv + r] = s;
+}
+
 // out (rows x nv, leading dimension ldo) = sum over nsplit partials (each
 // rows x nv, leading dimension ldp), keeping only the entries of row q in
 // column q % nv and zeroing the others: the coefficients of each Lanczos run
@@ -824,6 +926,18 @@ void sum_splits_diag(bool cplx, const void *P, int nsplit, int64_t sstride, int6
   else
     hipLaunchKernelGGL(k_sum_splits_diag<double>, grid, dim3(256), 0, s, (const double *)P, nsplit,
                        sstride, ldp, rows, nv, (double *)out, ldo);
+}
+
+void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void *W, int64_t ldw,
+                   double *ab, int k, hipStream_t s) {
+  if (N < 1 || N > kLzSmallMaxN || j < 0 || j >= k || k + 1 > kLzSmallMaxBasis || nv < 1)
+    throw InvalidArg();
+  if (cplx)
+    hipLaunchKernelGGL(k_lz_step_small<double2>, dim3(nv), dim3(256), 0, s, (double2 *)LV, ldv, N,
+                       j, nv, (double2 *)W, ldw, ab, k);
+  else
+    hipLaunchKernelGGL(k_lz_step_small<double>, dim3(nv), dim3(256), 0, s, (double *)LV, ldv, N, j,
+                       nv, (double *)W, ldw, ab, k);
 }
 
 static unsigned hh_blocks(int Mp, int jj) {

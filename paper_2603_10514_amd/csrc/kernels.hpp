@@ -60,6 +60,15 @@ void norm_scale_cols(bool cplx, const void *w, int64_t ldw, int n, int ncols, vo
 void sum_splits_diag(bool cplx, const void *P, int nsplit, int64_t sstride, int64_t ldp, int rows,
                      int nv, void *out, int64_t ldo, hipStream_t s);
 
+// One Lanczos step after the product for small orders (N <= kLzSmallMaxN,
+// k + 1 <= kLzSmallMaxBasis): alpha, two classical Gram-Schmidt passes
+// against the run's basis, beta and the next basis vector, one work-group
+// per run (layout as in the solver's Lanczos).
+constexpr int kLzSmallMaxN = 4096;
+constexpr int kLzSmallMaxBasis = 128;
+void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void *W, int64_t ldw,
+                   double *ab, int k, hipStream_t s);
+
 // Householder QR helpers (geqrf convention, panels of kHhNB columns).
 constexpr int kHhNB = 32;         // columns of one panel of column steps
 constexpr int kHhMaxOuter = 128;  // columns of one block reflector (T at most this wide)

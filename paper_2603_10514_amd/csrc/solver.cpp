@@ -690,10 +690,17 @@ void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const voi
   else
     randn(cplx, w.LW, N, (int)N, nv, seed, c.stream);
   norm_scale_cols(cplx, w.LW, N, (int)N, nv, w.LV, N, w.lz_ab + (size_t)k * nv, c.stream);
+  // small orders: the steps after the product in one launch (one work-group
+  // per run); otherwise several wide launches per step
+  const bool small = N <= kLzSmallMaxN && k + 1 <= kLzSmallMaxBasis;
   for (int j = 0; j < k; ++j) {
     const int nb = (j + 1) * nv;  // basis vectors so far, all runs
     void *Vj = (char *)w.LV + es * (size_t)N * j * nv;
     gemv_block(cplx, H, ldh, (int)N, (int)N, Vj, N, nv, w.LW, N, w.SK, w.sk_bytes, c.stream);
+    if (small) {
+      lz_step_small(cplx, w.LV, N, (int)N, j, nv, w.LW, N, w.lz_ab, k, c.stream);
+      continue;
+    }
     dot_re_cols(cplx, Vj, w.LW, N, (int)N, nv, w.lz_ab + (size_t)j * nv, c.stream);
     for (int rep = 0; rep < 2; ++rep) {
       GemmArgs a = gargs();

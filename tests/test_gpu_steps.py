@@ -201,11 +201,14 @@ def test_rayleigh_ritz_and_residuals(P, gpu, N, L, cplx):
 
 
 @pytest.mark.parametrize("N,cplx,nvec", [(1000, False, 1), (700, True, 1), (1000, False, 4),
-                                         (1537, True, 4), (333, False, 3), (2100, True, 8)])
+                                         (1537, True, 4), (333, False, 3), (2100, True, 8),
+                                         (4096, False, 2), (4097, True, 2)])
 def test_lanczos_matches_oracle(P, gpu, N, cplx, nvec):
     """nvec runs advanced as one block (the N x N product streams H once for
     all of them) against the oracle's runs one by one; sizes span one and
-    several row blocks and column splits of the product, with ragged ends."""
+    several row blocks and column splits of the product, with ragged ends,
+    and both forms of the step after the product (one work-group per run up
+    to order 4096, wide launches above)."""
     print("lanczos case", N, cplx, nvec, flush=True)
     H, lam = synth.planted_numpy(N, "dft", 15, cplx)
     V0 = synth.lanczos_starts(N, nvec, 16, cplx)
