@@ -481,6 +481,112 @@ __global__ __launch_bounds__(256) void k_lz_step_small(E *LV, int64_t ldv, int N
   if (t == 0) ab[(int64_t)(k + j) * nv + r] = s;
 }
 
+// --------------------------------------- small Hermitian eigensolver (Jacobi) --
+// Eigen-decomposition of a Hermitian n x n matrix, n <= kJacobiMaxN, by one
+// work-group: cyclic two-sided Jacobi in the parallel (round-robin) order,
+// each round applying n/2 disjoint rotations at once (columns of A and V,
+// then rows of A).  The 2 x 2 step for the pair (p, q) follows the symmetric
+// Schur decomposition of Golub and Van Loan (Sec. 8.5) after a phase that
+// makes a_pq real: with a_pq = |a_pq| e^{i phi}, tau = (a_qq - a_pp)/(2|a_pq|),
+// t = sign(tau)/(|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c,
+// J = [[c, s e^{i phi}], [-s e^{-i phi}, c]] and J^H A J zeroes a_pq.
+// Sweeps stop when the off-diagonal Frobenius norm falls below
+// 8 n u ||A||_F, at most kJacobiMaxSweeps; *info = 0, or 1 if that limit was
+// hit.  On exit A holds the eigenvectors as columns and theta the
+// eigenvalues, ascending (ties by index).
+template <typename E>
+__global__ __launch_bounds__(256) void k_jacobi_eig(E *A, int64_t lda, int n, double *theta,
+                                                    int *info) {
+  constexpr int MX = kJacobiMaxN;
+  __shared__ E sA[MX][MX + 1];
+  __shared__ E sV[MX][MX + 1];
+  __shared__ int sp[MX / 2], sq[MX / 2];
+  __shared__ double sc[MX / 2], ss[MX / 2];
+  __shared__ E sph[MX / 2];  // e^{i phi} of each pair
+  __shared__ double sh[256];
+  __shared__ int s_done;
+  const int t = threadIdx.x;
+  const int M = n + (n & 1);  // even order: an odd n gets an uncoupled extra index
+  for (int idx = t; idx < MX * MX; idx += 256) {
+    const int i = idx % MX, j = idx / MX;
+    E a = Num<E>::zero();
+    if (i < n && j < n) a = A[(int64_t)j * lda + i];
+    sA[i][j] = a;
+    sV[i][j] = Num<E>::real(i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  double fro = 0.0;
+  for (int idx = t; idx < M * M; idx += 256) fro += Num<E>::abs2(sA[idx % M][idx / M]);
+  fro = block_sum256(fro, sh);
+  const double stop = 8.0 * M * 0x1p-53 * sqrt(fro);
+  int sweep = 0;
+  for (; sweep < kJacobiMaxSweeps; ++sweep) {
+    double off = 0.0;
+    for (int idx = t; idx < M * M; idx += 256) {
+      const int i = idx % M, j = idx / M;
+      if (i != j) off += Num<E>::abs2(sA[i][j]);
+    }
+    off = block_sum256(off, sh);
+    if (t == 0) s_done = !(sqrt(off) > stop);
+    __syncthreads();
+    if (s_done) break;
+    for (int r = 0; r < M - 1; ++r) {
+      if (t < M / 2) {  // the round's pairs and their rotations
+        const int p = t == 0 ? r : (r + t) % (M - 1);
+        const int q = t == 0 ? M - 1 : (r - t + M - 1) % (M - 1);
+        const E apq = sA[p][q];
+        const double b = sqrt(Num<E>::abs2(apq));
+        double c = 1.0, s = 0.0;
+        E ph = Num<E>::real(1.0);
+        if (b > 0.0) {
+          const double tau = (Num<E>::re(sA[q][q]) - Num<E>::re(sA[p][p])) / (2.0 * b);
+          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+          ph = Num<E>::scale(apq, 1.0 / b);
+        }
+        sp[t] = p; sq[t] = q; sc[t] = c; ss[t] = s; sph[t] = ph;
+      }
+      __syncthreads();
+      // columns p, q of A and V: A J, V J
+      for (int idx = t; idx < (M / 2) * M * 2; idx += 256) {
+        const int k = idx % (M / 2), rest = idx / (M / 2), i = rest % M, which = rest / M;
+        E (*X)[MX + 1] = which == 0 ? sA : sV;
+        const int p = sp[k], q = sq[k];
+        const double c = sc[k], s = ss[k];
+        const E ph = sph[k];
+        const E xp = X[i][p], xq = X[i][q];
+        X[i][p] = Num<E>::scale(xp, c) - Num<E>::scale(Num<E>::mul(Num<E>::cj(ph), xq), s);
+        X[i][q] = Num<E>::scale(Num<E>::mul(ph, xp), s) + Num<E>::scale(xq, c);
+      }
+      __syncthreads();
+      // rows p, q of A: J^H A
+      for (int idx = t; idx < (M / 2) * M; idx += 256) {
+        const int k = idx % (M / 2), j = idx / (M / 2);
+        const int p = sp[k], q = sq[k];
+        const double c = sc[k], s = ss[k];
+        const E ph = sph[k];
+        const E ap = sA[p][j], aq = sA[q][j];
+        sA[p][j] = Num<E>::scale(ap, c) - Num<E>::scale(Num<E>::mul(ph, aq), s);
+        sA[q][j] = Num<E>::scale(Num<E>::mul(Num<E>::cj(ph), ap), s) + Num<E>::scale(aq, c);
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) info[0] = sweep == kJacobiMaxSweeps ? 1 : 0;
+  // ascending order: the rank of eigenvalue i among all (ties by index)
+  for (int i = t; i < n; i += 256) {
+    const double li = Num<E>::re(sA[i][i]);
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = Num<E>::re(sA[j][j]);
+      rank += (lj < li) || (lj == li && j < i);
+    }
+    theta[rank] = li;
+    for (int row = 0; row < n; ++row) A[(int64_t)rank * lda + row] = sV[row][i];
+  }
+}
+
 // out (rows x nv, leading dimension ldo) = sum over nsplit partials (each
 // rows x nv, leading dimension ldp), keeping only the entries of row q in
 // column q % nv and zeroing the others: the coefficients of each Lanczos run
@@ -938,6 +1044,17 @@ void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void 
   else
     hipLaunchKernelGGL(k_lz_step_small<double>, dim3(nv), dim3(256), 0, s, (double *)LV, ldv, N, j,
                        nv, (double *)W, ldw, ab, k);
+}
+
+void jacobi_eig(bool cplx, void *A, int64_t lda, int n, double *theta, int *info,
+                hipStream_t s) {
+  if (n < 1 || n > kJacobiMaxN || lda < n) throw InvalidArg();
+  if (cplx)
+    hipLaunchKernelGGL(k_jacobi_eig<double2>, dim3(1), dim3(256), 0, s, (double2 *)A, lda, n,
+                       theta, info);
+  else
+    hipLaunchKernelGGL(k_jacobi_eig<double>, dim3(1), dim3(256), 0, s, (double *)A, lda, n, theta,
+                       info);
 }
 
 static unsigned hh_blocks(int Mp, int jj) {

@@ -69,6 +69,14 @@ constexpr int kLzSmallMaxBasis = 128;
 void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void *W, int64_t ldw,
                    double *ab, int k, hipStream_t s);
 
+// Eigenvalues (ascending, theta) and eigenvectors (in place, columns of A)
+// of a Hermitian n x n matrix, n <= kJacobiMaxN, by one work-group (cyclic
+// Jacobi, parallel order); info[0] = 1 if kJacobiMaxSweeps did not converge.
+constexpr int kJacobiMaxN = 64;
+constexpr int kJacobiMaxSweeps = 40;
+void jacobi_eig(bool cplx, void *A, int64_t lda, int n, double *theta, int *info,
+                hipStream_t s);
+
 // Householder QR helpers (geqrf convention, panels of kHhNB columns).
 constexpr int kHhNB = 32;         // columns of one panel of column steps
 constexpr int kHhMaxOuter = 128;  // columns of one block reflector (T at most this wide)

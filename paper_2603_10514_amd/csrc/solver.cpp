@@ -642,14 +642,19 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
     gemm(cplx, false, true, false, false, GEMM_BIG, a, 1, c.stream);
   }
   gram(c, cplx, Q, ldq, N, Lp, w.A, 1, W, N);
-  rocblas_status st;
-  if (cplx)
-    st = rocsolver_zheevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp,
-                          (rocblas_double_complex *)w.A, Lp, w.theta, w.E, w.rinfo);
-  else
-    st = rocsolver_dsyevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp, (double *)w.A, Lp,
-                          w.theta, w.E, w.rinfo);
-  rocsolver_check(st, cplx ? "rocsolver_zheevd" : "rocsolver_dsyevd");
+  if (Lp <= kJacobiMaxN) {
+    // one work-group; the vendor divide-and-conquer costs dozens of launches
+    jacobi_eig(cplx, w.A, Lp, Lp, w.theta, w.rinfo, c.stream);
+  } else {
+    rocblas_status st;
+    if (cplx)
+      st = rocsolver_zheevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp,
+                            (rocblas_double_complex *)w.A, Lp, w.theta, w.E, w.rinfo);
+    else
+      st = rocsolver_dsyevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp, (double *)w.A,
+                            Lp, w.theta, w.E, w.rinfo);
+    rocsolver_check(st, cplx ? "rocsolver_zheevd" : "rocsolver_dsyevd");
+  }
   {
     GemmArgs a = bigargs(c);
     a.A = Q; a.lda = ldq;

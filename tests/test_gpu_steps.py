@@ -177,8 +177,11 @@ def test_householder_rank_deficient(P, gpu, cplx):
     assert np.linalg.norm(X - Q @ (Q.conj().T @ X)) <= 1e-13 * np.linalg.norm(X)
 
 
-@pytest.mark.parametrize("N,L,cplx", [(1000, 60, False), (600, 37, True), (200, 130, False)])
+@pytest.mark.parametrize("N,L,cplx", [(1000, 60, False), (600, 37, True), (200, 130, False),
+                                      (500, 64, True), (300, 1, False), (400, 65, True)])
 def test_rayleigh_ritz_and_residuals(P, gpu, N, L, cplx):
+    """Up to 64 columns the projected eigenproblem is solved by the library's
+    one-work-group Jacobi kernel, above by the vendor divide-and-conquer."""
     H, lam = synth.planted_numpy(N, "uniform", 13, cplx)
     Q, _ = np.linalg.qr(synth.start_block(N, L, 14, cplx))
     Q = np.asfortranarray(Q)
