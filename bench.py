@@ -12,9 +12,12 @@ nev = 1000, nex = 300, initial degree 20, optimised degrees in [10, 36],
 tol 1e-10, FP64.
 
 value = filter flops of the whole solve (8 N^2 per complex MatVec, 2 N^2 per
-real one, summed over every column's degree) / time-to-solution, in TFLOP/s.
-roofline: the filter kernel's algorithmic flops / its device time (HIP
-events recorded by the library around every filter phase on its stream).
+real one, summed over every column's degree: the paper's convention) /
+time-to-solution, in TFLOP/s.
+roofline: the filter kernel's executed flops (6 N^2 per complex MatVec, whose
+products run as three real MFMA products; 2 N^2 per real one) / its device
+time (HIP events recorded by the library around every filter phase on its
+stream), against the MFMA peak of the filter's precision.
 cpu_baseline: the CPU oracle's filter on a bounded sample of the same matrix.
 
     python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
@@ -302,13 +305,18 @@ def main():
     mv32 = sum(r["info"]["matvecs_fp32"] for r in results)
     t32 = sum(r["info"]["t_filter_fp32"] for r in results)
     mv64, t64 = matvecs - mv32, t_filter - t32
+    # executed flops per MatVec: complex products run as three real MFMA
+    # products (6 N^2 per complex MatVec), real ones as one (2 N^2); the
+    # paper's convention counts 8 N^2 per complex MatVec
+    fx = 6.0 if wl["cplx"] else 2.0
     if t32 > t64:
-        prec, kflops, ktime = "f32", f * float(N) ** 2 * mv32, t32
+        prec, kflops, ktime = "f32", fx * float(N) ** 2 * mv32, t32
     else:
-        prec, kflops, ktime = "f64", f * float(N) ** 2 * mv64, t64
+        prec, kflops, ktime = "f64", fx * float(N) ** 2 * mv64, t64
     achieved = kflops / ktime / 1e12
-    # per-step roofline (Sec. 8(d) of the design): step i with l'_i active
-    # columns cannot take less than max(f N^2 l'_i / peak, s (N^2 + 3 N l'_i) / HBM)
+    achieved_conv = achieved * f / fx
+    # per-step roofline: step i with l'_i active columns cannot take less
+    # than max(fx N^2 l'_i / peak, s (N^2 + 3 N l'_i) / HBM), executed flops
     es = (16.0 if wl["cplx"] else 8.0) / (2.0 if prec == "f32" else 1.0)
     t_star = 0.0
     for r in results:
@@ -318,9 +326,12 @@ def main():
             bpe = (16.0 if wl["cplx"] else 8.0) / (2.0 if x["filter_prec"] == 1 else 1.0)
             for i in range(1, int(d.max()) + 1 if d.size else 1):
                 lp = float(np.sum(d >= i))
-                t_star += max(f * float(N) ** 2 * lp / pk, bpe * (float(N) ** 2 + 3.0 * N * lp) / 8e12)
+                t_star += max(fx * float(N) ** 2 * lp / pk, bpe * (float(N) ** 2 + 3.0 * N * lp) / 8e12)
     scale = float(np.max(np.abs(lam)))
     eig_err = max(float(np.max(np.abs(r["evals"] - lam[:nev]))) / scale for r in results)
+    # per eigenvalue: max_i |lambda_i - planted_i| / |planted_i|
+    eig_err_each = max(float(np.max(np.abs(r["evals"] - lam[:nev]) / np.abs(lam[:nev])))
+                       for r in results)
     max_res = max(float(np.max(r["resid"])) for r in results)
     status_ok = all(r["status"] == P.CHASE_OK for r in results)
     phases = {k: sum(r["info"][k] for r in results) / len(results)
@@ -347,16 +358,23 @@ def main():
                    **({"mixed_buffer32": args.mixed_buffer32} if wl["precision"] else {})},
         "time_to_solution_s": wall / args.steps,
         "filter_tflops": flops / t_filter / 1e12,
+        "filter_tflops_basis": "%d N^2 flops per MatVec (the paper's convention)" % int(f),
         "filter_frac_of_per_step_roofline": t_star / t_filter,
         "matvecs_per_solve": matvecs / args.steps,
         "iters_per_solve": iters / args.steps,
         "phase_s_per_solve": phases,
         "qr_variants": variants[0],
         "max_eig_err_rel": eig_err,
+        "max_eig_err_rel_per_eigenvalue": eig_err_each,
         "max_resid": max_res,
         "converged": status_ok,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec],
                      "unit": "TFLOP/s", "frac": achieved / PEAK[prec],
+                     "flops_basis": "executed MFMA flops: %s N^2 per MatVec (%s)" % (
+                         int(fx), "three real products per complex product" if wl["cplx"]
+                         else "one real product"),
+                     "achieved_paper_convention": achieved_conv,
+                     "paper_convention": "%d N^2 flops per MatVec" % int(f),
                      "traffic": measured_traffic(args.workload),
                      "traffic_unit": "bytes per filter dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      # es (N^2 + 3 N l') per degree step (H once; X, X_prev and the
@@ -364,18 +382,18 @@ def main():
                      "algorithmic_bytes_per_dispatch": (16.0 if wl["cplx"] else 8.0) * (
                          float(N) ** 2 * n_steps + 3.0 * N * matvecs) / max(launches, 1),
                      "kernel": "filter GEMM (gemm_kernel, EPI_FILTER, %s)" % prec,
-                     # complex products run as three real MFMA products, so
-                     # the MFMA units execute 3/4 of the algorithmic flops
-                     "mfma_executed_tflops": achieved * (0.75 if wl["cplx"] else 1.0),
-                     "mfma_busy_frac": achieved * (0.75 if wl["cplx"] else 1.0) / PEAK[prec],
                      "launches": launches, "avg_launch_ms": t_filter / max(launches, 1) * 1e3,
-                     "flops_per_launch": flops / max(launches, 1)},
+                     "executed_flops_per_launch": fx * float(N) ** 2 * matvecs / max(launches, 1)},
     }
     if wl["precision"] == 1:
         r32 = f * float(N) ** 2 * mv32 / max(t32, 1e-12) / 1e12
         r64 = f * float(N) ** 2 * mv64 / max(t64, 1e-12) / 1e12
-        out["mixed"] = {"fp32_filter_tflops": r32, "fp32_frac_of_peak": r32 / PEAK["f32"],
-                        "fp64_filter_tflops": r64, "fp64_frac_of_peak": r64 / PEAK["f64"],
+        # fractions of peak on executed flops (fx per MatVec), rates in the
+        # paper's convention (f per MatVec)
+        out["mixed"] = {"fp32_filter_tflops": r32,
+                        "fp32_frac_of_peak": r32 * fx / f / PEAK["f32"],
+                        "fp64_filter_tflops": r64,
+                        "fp64_frac_of_peak": r64 * fx / f / PEAK["f64"],
                         "fp32_matvec_share": mv32 / max(matvecs, 1),
                         "fp32_filter_time_share": t32 / max(t_filter, 1e-12),
                         "fp32_iters_per_solve": fp32_iters / args.steps}

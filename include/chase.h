@@ -81,6 +81,10 @@ typedef struct chase_iter_log {
   double c, e, gamma, lam1; /* filter centre, half-width, normalisation point,
                                lowest Ritz value (the rho_1 point)              */
   double t_filter, t_qr, t_rr, t_resid; /* seconds, device events               */
+  double qr_fro2;        /* shifted branch of Alg. 3: ||X||_F^2 = trace(X^H X) of
+                            the block [Y | filtered]; NaN on the other branches */
+  double qr_shift;       /* the shift s = 11 (N l + l (l + 1)) u ||X||_F^2 added
+                            to the Gram matrix (u = 2^-53); NaN otherwise        */
   int32_t ncols;         /* active (filtered) columns of this iteration        */
   const int32_t *degrees; /* their degrees, ascending (valid during log_cb)    */
 } chase_iter_log;
@@ -222,14 +226,22 @@ void chase_degrees(const double *theta, const double *resid, int32_t ncols, doub
                    double c, double e, int32_t min_deg, int32_t max_deg, int32_t margin,
                    int32_t *degrees_out);
 
-/* Orthonormalise X (device, N x ncols, in place) with one QR variant.
+/* Orthonormalise X (device, N x ncols, in place) with one QR variant
+ * (Alg. 2 for CHOL1 / CHOL2, Alg. 3's shifted pass followed by CholeskyQR2
+ * for SHIFTED, Householder QR).
  * chol_failed (host, may be NULL) is set to 1 when a Cholesky failed and the
- * Householder QR was applied to the block as it stood before that pass. */
+ * Householder QR was applied to the block as it stood before that pass.
+ * shift (host [2], may be NULL): for SHIFTED, shift[0] = ||X||_F^2 (the trace
+ * of the Gram matrix the library formed) and shift[1] = the shift
+ * 11 (N ncols + ncols (ncols + 1)) 2^-53 shift[0] that it added to that Gram
+ * matrix's diagonal (Alg. 3); NaN for the other variants. */
 chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx, int32_t ncols,
-                             chase_qr variant, int32_t *chol_failed, void *stream);
+                             chase_qr variant, int32_t *chol_failed, double *shift,
+                             void *stream);
 
 /* Rayleigh-Ritz on an orthonormal Q (device, N x ncols): ritz (host, ascending),
- * V = Q Z and HV = H Q Z (device, N x ncols). */
+ * V = Q Z and HV = H Q Z (device, N x ncols).  CHASE_EDEVICE if the
+ * eigensolver of the projected ncols x ncols matrix reports no convergence. */
 chase_status chase_rayleigh_ritz(chase_dtype dtype, const void *H, int64_t N, int64_t ldh,
                                  const void *Q, int64_t ldq, int32_t ncols, double *ritz,
                                  void *V, int64_t ldv, void *HV, int64_t ldhv, void *stream);
@@ -270,6 +282,18 @@ chase_status chase_lanczos(chase_dtype dtype, const void *H, int64_t N, int64_t 
  * or nsearch outside 1..N. */
 chase_status chase_lanczos_bounds(const double *alpha, const double *beta, int32_t nvec,
                                   int32_t steps, int64_t N, int32_t nsearch, double *bounds);
+
+/* Bounds for the next problem of a sequence H_{j+1} = H_j + D (host only):
+ * a warm start (Alg. 1 takes an optional start block and optional spectral
+ * bounds) reuses the previous problem's subspace and bounds, and by Weyl's
+ * inequality every eigenvalue moves by at most ||D||_2.  prev [3] = (lowest
+ * Ritz value, largest Ritz value of the search space, upper bound) of the
+ * previous solve (evals[0], info.ritz_max, info.lambda_max); delta >= ||D||_2
+ * (a bound the caller knows).  out [3] = (prev[0] - delta, prev[1],
+ * prev[2] + delta), ready for opts.lambda_1 / lambda_l / lambda_max.
+ * Errors: EINVAL for NULL pointers, delta < 0 or non-finite values, or
+ * prev not ordered (prev[0] <= prev[1] < prev[2]). */
+chase_status chase_sequence_bounds(const double *prev, double delta, double *out);
 
 const char *chase_strerror(chase_status s);
 const char *chase_last_error(void);

@@ -33,7 +33,7 @@ from .degrees import optimised_degrees
 from .estimate import cond_estimate, select_variant
 from .filter import chebyshev_filter
 from .lanczos import lanczos_bounds
-from .qr import CholeskyFailure, cholqr, dynamic_caqr, householder_qr
+from .qr import CholeskyFailure, cholqr, dynamic_caqr, householder_qr, shift_value
 from .rr import rayleigh_ritz, residual_norms
 
 
@@ -122,6 +122,7 @@ def chase_solve(H, nev, nex, deg=20, tol=1e-10, *, V0, bounds=None,
         res_locked.extend(r[:newly].tolist())
         log.append(dict(iter=it, locked=k, cond_est=est, cond_exact=kappa,
                         variant=variant, chol_failed=bool(failed),
+                        qr_shift=shift_value(X) if variant == "shifted" else None,
                         matvecs=int(m.sum()), deg_max=int(m.max()),
                         deg_min=int(m.min()), newly_locked=newly,
                         c=c, e=e, gamma=gamma, lam1=lam1))

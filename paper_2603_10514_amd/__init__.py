@@ -39,7 +39,8 @@ class ChaseIterLog(ctypes.Structure):
                 ("e", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("lam1", ctypes.c_double), ("t_filter", ctypes.c_double),
                 ("t_qr", ctypes.c_double), ("t_rr", ctypes.c_double),
-                ("t_resid", ctypes.c_double), ("ncols", ctypes.c_int32),
+                ("t_resid", ctypes.c_double), ("qr_fro2", ctypes.c_double),
+                ("qr_shift", ctypes.c_double), ("ncols", ctypes.c_int32),
                 ("degrees", ctypes.POINTER(ctypes.c_int32))]
 
 
@@ -110,13 +111,15 @@ _sig("chase_filter", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _p, _i64, _i64, 
 _sig("chase_log_cond_estimate", _d, [_d, _i32, _i32, _d, _d, _d])
 _sig("chase_select_qr", ctypes.c_int, [_d, _d, _d])
 _sig("chase_degrees", None, [_dp, _dp, _i32, _d, _d, _d, _i32, _i32, _i32, _ip])
-_sig("chase_qr_factor", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _i32, ctypes.c_int, _ip, _p])
+_sig("chase_qr_factor", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _i32, ctypes.c_int, _ip, _dp,
+                                       _p])
 _sig("chase_rayleigh_ritz", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i64, _i32, _dp,
                                            _p, _i64, _p, _i64, _p])
 _sig("chase_residuals", ctypes.c_int, [ctypes.c_int, _p, _i64, _p, _i64, _i64, _i32, _dp, _dp, _p])
 _sig("chase_lanczos", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i32, _i32, _i32, _dp, _dp,
                                      _dp, _p])
 _sig("chase_lanczos_bounds", ctypes.c_int, [_dp, _dp, _i32, _i32, _i64, _i32, _dp])
+_sig("chase_sequence_bounds", ctypes.c_int, [_dp, _d, _dp])
 _sig("chase_strerror", ctypes.c_char_p, [ctypes.c_int])
 _sig("chase_last_error", ctypes.c_char_p, [])
 
@@ -305,15 +308,20 @@ def chase_degrees(theta, resid, tol, c, e, min_deg=1, max_deg=36, margin=2):
     return out
 
 
-def chase_qr_factor(X, variant, stream=None):
-    """Orthonormalise X in place with one variant; returns chol_failed."""
+def chase_qr_factor(X, variant, stream=None, return_shift=False):
+    """Orthonormalise X in place with one variant; returns chol_failed, or
+    (chol_failed, (||X||_F^2, shift)) with return_shift (NaN unless the
+    variant is "shifted")."""
     if isinstance(variant, str):
         variant = QR_CODES[variant]
     xp, ldx = _colmajor(X, "X")
     failed = ctypes.c_int32(0)
+    sh = np.zeros(2)
     st = lib.chase_qr_factor(_dtype_code(X), xp, X.shape[0], ldx, X.shape[1], variant,
-                             ctypes.byref(failed), _stream_ptr(stream))
+                             ctypes.byref(failed), sh.ctypes.data_as(_dp), _stream_ptr(stream))
     _check(st, "chase_qr_factor")
+    if return_shift:
+        return bool(failed.value), (float(sh[0]), float(sh[1]))
     return bool(failed.value)
 
 
@@ -373,6 +381,19 @@ def chase_lanczos_bounds(alpha, beta, N, nsearch):
                                   a.shape[1], N, nsearch, bounds.ctypes.data_as(_dp))
     _check(st, "chase_lanczos_bounds")
     return tuple(bounds)
+
+
+def chase_sequence_bounds(prev, delta):
+    """Bounds for the next problem of a sequence H + D with ||D||_2 <= delta,
+    from the previous solve's (lowest Ritz value, largest Ritz value of the
+    search space, upper bound)."""
+    p = np.ascontiguousarray(prev, dtype=np.float64)
+    if p.size != 3:
+        raise ValueError("prev must hold three values")
+    out = np.zeros(3)
+    _check(lib.chase_sequence_bounds(p.ctypes.data_as(_dp), float(delta),
+                                     out.ctypes.data_as(_dp)), "chase_sequence_bounds")
+    return tuple(float(x) for x in out)
 
 
 # ------------------------------------------------------ async handles -----

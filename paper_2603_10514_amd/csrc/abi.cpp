@@ -1,6 +1,7 @@
 // extern "C" entry points declared in include/chase.h: argument checks,
 // error mapping, asynchronous handles and the per-step entry points.
 #include <atomic>
+#include <cmath>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -285,7 +286,8 @@ void chase_degrees(const double *theta, const double *resid, int32_t ncols, doub
 }
 
 chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx, int32_t ncols,
-                             chase_qr variant, int32_t *chol_failed, void *stream) {
+                             chase_qr variant, int32_t *chol_failed, double *shift,
+                             void *stream) {
   if (!dtype_ok(dtype)) return fail(CHASE_EINVAL, "unknown dtype");
   if (!X) return fail(CHASE_EINVAL, "X is NULL");
   if (N < 1 || ncols < 1 || ncols > N || ldx < N) return fail(CHASE_EINVAL, "invalid sizes");
@@ -310,6 +312,10 @@ chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx,
       throw DeviceError();
     }
     if (chol_failed) *chol_failed = q.failed ? 1 : 0;
+    if (shift) {
+      shift[0] = q.fro2;
+      shift[1] = q.shift;
+    }
     return CHASE_OK;
   });
 }
@@ -331,11 +337,17 @@ chase_status chase_rayleigh_ritz(chase_dtype dtype, const void *H, int64_t N, in
     rayleigh_ritz(cx, cplx, H, ldh, N, Q, ldq, ncols, cx.w.B2, V, ldv, HV, ldhv);
     CHASE_HIP(hipMemcpyAsync(ritz, cx.w.theta, 8 * (size_t)ncols, hipMemcpyDeviceToHost,
                              cx.stream));
+    CHASE_HIP(hipMemcpyAsync(cx.w.h_flag + 2, cx.w.rinfo, 4, hipMemcpyDeviceToHost, cx.stream));
     hipError_t err = hipStreamSynchronize(cx.stream);
     cx.stream = own;
     cx.set_stream(own);
     if (err != hipSuccess) {
       set_error(std::string("rayleigh_ritz: ") + hipGetErrorString(err));
+      throw DeviceError();
+    }
+    if (cx.w.h_flag[2] != 0) {
+      set_error("rayleigh_ritz: the projected eigenproblem did not converge (info " +
+                std::to_string(cx.w.h_flag[2]) + ")");
       throw DeviceError();
     }
     return CHASE_OK;
@@ -405,6 +417,20 @@ chase_status chase_lanczos_bounds(const double *alpha, const double *beta, int32
     lanczos_bounds_from_runs(a, b, nvec, N, nsearch, bounds);
     return CHASE_OK;
   });
+}
+
+chase_status chase_sequence_bounds(const double *prev, double delta, double *out) {
+  if (!prev || !out) return fail(CHASE_EINVAL, "NULL argument");
+  if (!(delta >= 0.0) || !std::isfinite(delta) || !std::isfinite(prev[0]) ||
+      !std::isfinite(prev[1]) || !std::isfinite(prev[2]))
+    return fail(CHASE_EINVAL, "delta must be >= 0 and the bounds finite");
+  if (!(prev[0] <= prev[1] && prev[1] < prev[2]))
+    return fail(CHASE_EINVAL, "need prev[0] <= prev[1] < prev[2]");
+  const double lo = prev[0] - delta, mid = prev[1], hi = prev[2] + delta;
+  out[0] = lo;
+  out[1] = mid;
+  out[2] = hi;
+  return CHASE_OK;
 }
 
 const char *chase_strerror(chase_status s) {

@@ -297,7 +297,9 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int
     CHASE_HIP(hipHostMalloc((void **)&w.h_resid, 8 * (size_t)h_cap_L));
     CHASE_HIP(hipHostMalloc((void **)&w.h_ab, 16 * (size_t)h_cap_lz));
     CHASE_HIP(hipHostMalloc((void **)&w.h_flag, 16));
-    CHASE_HIP(hipHostMalloc((void **)&w.h_ints, 8 * (size_t)h_cap_L));
+    CHASE_HIP(hipHostMalloc((void **)&w.h_aux, 32));
+    CHASE_HIP(hipHostMalloc((void **)&w.h_perm, 4 * (size_t)h_cap_L));
+    CHASE_HIP(hipHostMalloc((void **)&w.h_deg, 4 * (size_t)h_cap_L));
   }
 }
 
@@ -306,9 +308,11 @@ void Ctx::free_pinned() {
   if (w.h_resid) (void)hipHostFree(w.h_resid);
   if (w.h_ab) (void)hipHostFree(w.h_ab);
   if (w.h_flag) (void)hipHostFree(w.h_flag);
-  if (w.h_ints) (void)hipHostFree(w.h_ints);
-  w.h_theta = w.h_resid = w.h_ab = nullptr;
-  w.h_flag = w.h_ints = nullptr;
+  if (w.h_aux) (void)hipHostFree(w.h_aux);
+  if (w.h_perm) (void)hipHostFree(w.h_perm);
+  if (w.h_deg) (void)hipHostFree(w.h_deg);
+  w.h_theta = w.h_resid = w.h_ab = w.h_aux = nullptr;
+  w.h_flag = w.h_perm = w.h_deg = nullptr;
   h_cap_L = h_cap_lz = 0;
 }
 
@@ -594,38 +598,66 @@ static void householder(Ctx &c, bool cplx, void *X, void *V, int64_t ld, int64_t
 // Alg. 3 for one variant.  The passes of CholeskyQR (Alg. 2) alternate
 // between X and Xalt; after a failed Cholesky every later kernel of the QR
 // sees the flag and does nothing, so the input of the failing pass is intact
-// and the Householder QR is applied to it.
-QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, chase_qr variant,
-         int inject) {
+// and the Householder QR is applied to it.  The flag (and, on the shifted
+// branch, ||X||_F^2 and the shift) are copied to pinned host memory on the
+// stream; qr_finish reads them once the caller has synchronised.
+QrPending qr_enqueue(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L,
+                     chase_qr variant, int inject) {
   Work &w = c.w;
+  QrPending p;
+  std::memset(&p, 0, sizeof(p));
+  p.X = X;
+  p.Xalt = Xalt;
+  p.variant = variant;
+  w.h_flag[0] = w.h_flag[1] = 0;
+  w.h_aux[0] = w.h_aux[1] = NAN;
   if (variant == CHASE_QR_HOUSEHOLDER) {
     householder(c, cplx, X, Xalt, ld, N, L);
-    return {X, false, CHASE_QR_HOUSEHOLDER};
+    p.npass = 0;
+    p.out = X;
+    return p;
   }
-  int npass = variant == CHASE_QR_CHOL1 ? 1 : variant == CHASE_QR_CHOL2 ? 2 : 3;
+  p.npass = variant == CHASE_QR_CHOL1 ? 1 : variant == CHASE_QR_CHOL2 ? 2 : 3;
   const bool shifted = variant == CHASE_QR_SHIFTED;
   fill_zero(false, w.flag, 1, 1, 1, c.stream);  // two ints
   void *in = X;
-  void *inputs[3];
+  // shift s = 11 (N L + L (L + 1)) u ||X||_F^2 with ||X||_F^2 = trace(X^H X)
   const double coef = 11.0 * ((double)N * L + (double)L * (L + 1)) * kUnitRoundoff;
-  for (int q = 0; q < npass; ++q) {
+  for (int q = 0; q < p.npass; ++q) {
     void *out = (in == X) ? Xalt : X;
-    inputs[q] = in;
+    p.inputs[q] = in;
     gram(c, cplx, in, ld, N, L, w.G, 0);
     if (shifted && q == 0) trace_shift(cplx, w.G, L, L, coef, 1, w.trace, w.flag, c.stream);
     potrf(c, cplx, L, q, inject && q == 0);
     trsm(c, cplx, in, out, ld, N, L);
     in = out;
   }
+  p.out = in;
   CHASE_HIP(hipGetLastError());
   CHASE_HIP(hipMemcpyAsync(w.h_flag, w.flag, 8, hipMemcpyDeviceToHost, c.stream));
-  CHASE_HIP(hipStreamSynchronize(c.stream));
-  if (w.h_flag[0] != 0) {
-    const int fp = std::min(std::max(w.h_flag[1], 0), npass - 1);
-    householder(c, cplx, inputs[fp], inputs[fp] == X ? Xalt : X, ld, N, L);
-    return {inputs[fp], true, CHASE_QR_HOUSEHOLDER};
+  if (shifted)
+    CHASE_HIP(hipMemcpyAsync(w.h_aux, w.trace, 16, hipMemcpyDeviceToHost, c.stream));
+  return p;
+}
+
+QrOut qr_finish(Ctx &c, bool cplx, const QrPending &p, int64_t ld, int64_t N, int L) {
+  Work &w = c.w;
+  const double fro2 = p.variant == CHASE_QR_SHIFTED ? w.h_aux[0] : NAN;
+  const double shift = p.variant == CHASE_QR_SHIFTED ? w.h_aux[1] : NAN;
+  if (p.npass > 0 && w.h_flag[0] != 0) {
+    const int fp = std::min(std::max(w.h_flag[1], 0), p.npass - 1);
+    void *in = p.inputs[fp];
+    householder(c, cplx, in, in == p.X ? p.Xalt : p.X, ld, N, L);
+    return {in, true, CHASE_QR_HOUSEHOLDER, fro2, shift};
   }
-  return {in, false, variant};
+  return {p.out, false, p.variant, fro2, shift};
+}
+
+QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, chase_qr variant,
+         int inject) {
+  QrPending p = qr_enqueue(c, cplx, X, Xalt, ld, N, L, variant, inject);
+  CHASE_HIP(hipStreamSynchronize(c.stream));
+  return qr_finish(c, cplx, p, ld, N, L);
 }
 
 // Rayleigh-Ritz on the orthonormal Q (N x Lp): W = H Q, A~ = Q^H W
@@ -823,15 +855,16 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     auto by_degree = [&](int a, int b) { return m[a] < m[b]; };
     std::stable_sort(order.begin(), order.begin() + nW, by_degree);
     std::stable_sort(order.begin() + nW, order.end(), by_degree);
+    // permutation and degrees go up from their own pinned mirrors, which the
+    // host rewrites only after the next end-of-iteration synchronisation
     std::vector<int> msorted(Lp);
     for (int a = 0; a < Lp; ++a) {
       msorted[a] = m[order[a]];
-      w.h_ints[a] = order[a] + k;
+      w.h_perm[a] = order[a] + k;
+      w.h_deg[a] = msorted[a];
     }
-    CHASE_HIP(hipMemcpyAsync(w.perm, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
-    CHASE_HIP(hipStreamSynchronize(s));  // h_ints is reused below
-    for (int a = 0; a < Lp; ++a) w.h_ints[a] = msorted[a];
-    CHASE_HIP(hipMemcpyAsync(w.deg, w.h_ints, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
+    CHASE_HIP(hipMemcpyAsync(w.perm, w.h_perm, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
+    CHASE_HIP(hipMemcpyAsync(w.deg, w.h_deg, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
     void *bufs[3] = {w.X0, w.B1, w.B2};
     gather_cols(cplx, f32, evecs, ldv, w.X0, N, (int)N, nW, w.perm, s);
     CHASE_HIP(hipEventRecord(c.ev[0], s));
@@ -867,23 +900,49 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
       CHASE_HIP(hipStreamSynchronize(s));
       kappa = o.block_cb(w.Xq, N, N, L, it, o.block_user);
     }
-    QrOut q = qr(c, cplx, w.Xq, w.B1, N, N, L, variant, o.inject_chol_fail_iter == it);
+    // QR, Rayleigh-Ritz and residuals are enqueued back to back; the QR's
+    // failure flag, the eigensolver's info and the Ritz values and residuals
+    // come back with one synchronisation.  After a Cholesky failure (rare)
+    // the Householder QR runs on the failing pass's input and Rayleigh-Ritz
+    // and the residuals are redone on its Q.
+    QrPending qp = qr_enqueue(c, cplx, w.Xq, w.B1, N, N, L, variant, o.inject_chol_fail_iter == it);
     CHASE_HIP(hipEventRecord(c.ev[2], s));
-    void *Q2 = (char *)q.Q + es * (size_t)k * N;
     void *Vout = (char *)evecs + es * (size_t)k * ldv;
-    rayleigh_ritz(c, cplx, H, ldh, N, Q2, N, Lp, w.B2, Vout, ldv, w.X0, N);
-    CHASE_HIP(hipEventRecord(c.ev[3], s));
-    residuals(cplx, w.X0, N, Vout, ldv, (int)N, Lp, w.theta, w.resid, s);
-    CHASE_HIP(hipEventRecord(c.ev[4], s));
-    CHASE_HIP(hipMemcpyAsync(w.h_theta, w.theta, 8 * (size_t)Lp, hipMemcpyDeviceToHost, s));
-    CHASE_HIP(hipMemcpyAsync(w.h_resid, w.resid, 8 * (size_t)Lp, hipMemcpyDeviceToHost, s));
-    CHASE_HIP(hipStreamSynchronize(s));
+    auto rr_resid = [&](const void *Qbuf) {
+      const void *Q2 = (const char *)Qbuf + es * (size_t)k * N;
+      rayleigh_ritz(c, cplx, H, ldh, N, Q2, N, Lp, w.B2, Vout, ldv, w.X0, N);
+      CHASE_HIP(hipEventRecord(c.ev[3], s));
+      residuals(cplx, w.X0, N, Vout, ldv, (int)N, Lp, w.theta, w.resid, s);
+      CHASE_HIP(hipEventRecord(c.ev[4], s));
+      CHASE_HIP(hipMemcpyAsync(w.h_theta, w.theta, 8 * (size_t)Lp, hipMemcpyDeviceToHost, s));
+      CHASE_HIP(hipMemcpyAsync(w.h_resid, w.resid, 8 * (size_t)Lp, hipMemcpyDeviceToHost, s));
+      CHASE_HIP(hipMemcpyAsync(w.h_flag + 2, w.rinfo, 4, hipMemcpyDeviceToHost, s));
+      CHASE_HIP(hipStreamSynchronize(s));
+    };
+    rr_resid(qp.out);
+    double t_qr = elapsed(c.ev[1], c.ev[2]), t_rr = elapsed(c.ev[2], c.ev[3]);
+    double t_res = elapsed(c.ev[3], c.ev[4]);
+    QrOut q = qr_finish(c, cplx, qp, N, N, L);
+    if (q.failed) {
+      CHASE_HIP(hipEventRecord(c.ev[2], s));  // after the Householder QR of qr_finish
+      rr_resid(q.Q);
+      t_qr += elapsed(c.ev[4], c.ev[2]);  // approximate: the redo's QR span
+      t_rr += elapsed(c.ev[2], c.ev[3]);
+      t_res += elapsed(c.ev[3], c.ev[4]);
+    }
+    if (w.h_flag[2] != 0) {
+      set_error("Rayleigh-Ritz: the projected eigenproblem did not converge (info " +
+                std::to_string(w.h_flag[2]) + ")");
+      throw DeviceError();
+    }
     chase_iter_log rec;
     std::memset(&rec, 0, sizeof(rec));
     rec.t_filter = elapsed(c.ev[0], c.ev[1]);
-    rec.t_qr = elapsed(c.ev[1], c.ev[2]);
-    rec.t_rr = elapsed(c.ev[2], c.ev[3]);
-    rec.t_resid = elapsed(c.ev[3], c.ev[4]);
+    rec.t_qr = t_qr;
+    rec.t_rr = t_rr;
+    rec.t_resid = t_res;
+    rec.qr_fro2 = q.fro2;
+    rec.qr_shift = q.shift;
     inf.t_filter += rec.t_filter; inf.t_qr += rec.t_qr; inf.t_rr += rec.t_rr;
     if (f32) {
       inf.t_filter_fp32 += rec.t_filter;

@@ -31,7 +31,9 @@ struct Work {
   size_t sk_bytes = 0;
   // pinned host mirrors
   double *h_theta = nullptr, *h_resid = nullptr, *h_ab = nullptr;
-  int *h_flag = nullptr, *h_ints = nullptr;
+  double *h_aux = nullptr;  // [0] ||X||_F^2, [1] shift of the last shifted pass
+  int *h_flag = nullptr;    // [0..1] QR failure flag, [2] eigensolver info
+  int *h_perm = nullptr, *h_deg = nullptr;
 };
 
 size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec);
@@ -71,10 +73,26 @@ int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, v
            int64_t ldb, int ncols, const int *deg_dev, const std::vector<int> &deg_sorted,
            double cc, double e, double gamma, void *out, int64_t ldo);
 struct QrOut {
-  void *Q;
-  bool failed;
+  void *Q;          // buffer that holds Q
+  bool failed;      // a Cholesky failed and the Householder QR ran instead
   chase_qr ran;
+  double fro2, shift;  // shifted branch: ||X||_F^2 = trace(X^H X) and the shift; NaN otherwise
 };
+// A QR whose Cholesky passes are enqueued but whose failure flag has not been
+// read yet (it is copied to the pinned mirror h_flag on the stream).
+struct QrPending {
+  void *X, *Xalt;
+  void *inputs[3];
+  int npass;
+  chase_qr variant;
+  void *out;  // where Q lands when no Cholesky fails
+};
+QrPending qr_enqueue(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L,
+                     chase_qr variant, int inject);
+// After the stream has been synchronised: read the flag; on a failure enqueue
+// the Householder QR of the failing pass's input (not synchronised).
+QrOut qr_finish(Ctx &c, bool cplx, const QrPending &p, int64_t ld, int64_t N, int L);
+// qr_enqueue, synchronise, qr_finish.
 QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, chase_qr variant,
          int inject);
 void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *Q,

@@ -6,12 +6,15 @@ H_{j+1} = H_j + eps * E_j (E_j Hermitian Gaussian, E|g|^2 = 1, scaled by
 previous problem's subspace, which stays in device memory (the warm start of
 Sec. 1.2 of the paper).  The scheduler:
 
-* keeps a FIFO of arrived requests and a fixed set of slots, each owning a
-  library handle (own stream, workspace sized for the largest problem, host
-  worker thread), so solves of different requests overlap on the device;
-* admits the head of the queue into a free slot when the request's device
-  memory (working matrix, perturbation scratch, search block, the part of
-  the workspace the slot does not already hold) fits the HBM budget;
+* keeps a queue of arrived requests (arrival order) and a fixed set of
+  slots, each owning a library handle (own stream, workspace sized for the
+  largest problem, host worker thread), so solves of different requests
+  overlap on the device;
+* admits into a free slot the oldest waiting request whose device memory
+  (working matrix, perturbation scratch, search block) fits the HBM budget:
+  a later request may overtake an older one that does not fit, but only
+  `max_bypass` times, after which the oldest one is admitted first (no
+  starvation);
 * keeps an admitted request in its slot for all its steps (continuous
   batching: a slot frees, the next request enters while the others run);
 * records, per request, arrival-to-completion latency and every step's
@@ -44,6 +47,8 @@ class Request:
     eps: float = 1e-3
     seed: int = 0
     # results
+    bypassed: int = 0       # times a later request was admitted before this one
+    captured: list = field(default_factory=list)  # (V0, bounds) per step, capture mode
     t_admit: float = None
     t_done: float = None
     evals: list = field(default_factory=list)
@@ -83,7 +88,7 @@ class Slot:
 class Server:
     def __init__(self, n_slots=4, N_max=25000, nev_max=None, nex_max=None, precision=P.PREC_MIXED,
                  hbm_budget=None, reserve=16 * GIB, degree=20, tol=1e-10, min_deg=10, max_deg=36,
-                 device="cuda:0", cplx=True):
+                 device="cuda:0", cplx=True, max_bypass=4, capture=False):
         import torch
         self.device = torch.device(device)
         self.cplx = cplx
@@ -104,6 +109,10 @@ class Server:
         self.peak_used = 0
         self.degree, self.tol = degree, tol
         self.N_max, self.nev_max, self.nex_max = N_max, nev_max, nex_max
+        self.max_bypass = max_bypass
+        # capture: keep a host copy of every step's start block and bounds
+        # (for checking the steps one by one against a reference solver)
+        self.capture = capture
         self.log = []
 
     # ------------------------------------------------------------------ API
@@ -139,16 +148,18 @@ class Server:
                 progressed = True
                 if s.req is None:
                     done += 1
-            # admission (FIFO, head of line)
+            # admission: the oldest request that fits, with bounded bypass
             for s in self.slots:
                 if s.req is not None or not waiting:
                     continue
-                r = waiting[0]
-                need = data_bytes(r.N, r.nev, r.nex, self.cplx)
-                if self.used + need > self.budget:
+                pick = self._pick(waiting)
+                if pick is None:
                     break
-                waiting.pop(0)
-                self._admit(s, r, need, time.perf_counter() - t0)
+                r = waiting.pop(pick)
+                for older in waiting[:pick]:
+                    older.bypassed += 1
+                self._admit(s, r, data_bytes(r.N, r.nev, r.nex, self.cplx),
+                            time.perf_counter() - t0)
                 progressed = True
             if not progressed:
                 if nxt < len(reqs) and not waiting and all(s.req is None for s in self.slots):
@@ -160,6 +171,17 @@ class Server:
     def close(self):
         for s in self.slots:
             s.handle.close()
+
+    def _pick(self, waiting):
+        """Index of the request to admit next, or None.  The oldest waiting
+        request goes first when it fits; a later one that fits may overtake
+        it unless the oldest has already been overtaken max_bypass times."""
+        for i, r in enumerate(waiting):
+            if self.used + data_bytes(r.N, r.nev, r.nex, self.cplx) <= self.budget:
+                return i
+            if r.bypassed >= self.max_bypass:
+                return None  # hold the memory that frees up for this one
+        return None
 
     # ------------------------------------------------------------- internals
     def _admit(self, s, r, need, now):
@@ -174,7 +196,12 @@ class Server:
             s.Hk = torch.empty_strided(r.H0.shape, r.H0.stride(), dtype=r.H0.dtype,
                                        device=self.device)
             s.Hk.copy_(r.H0)
-            s.evecs = P.colmajor_empty(r.N, r.nev + r.nex, r.H0.dtype, self.device)
+            # Gaussian start block of the first problem (Alg. 1's random
+            # V0): real N(0,1), complex (N(0,1) + i N(0,1)) / sqrt(2)
+            g = torch.Generator(device=self.device)
+            g.manual_seed(int(r.seed) * 7919 + 1)
+            s.evecs = torch.randn((r.nev + r.nex, r.N), dtype=r.H0.dtype, device=self.device,
+                                  generator=g).T
         s.bounds = None
         self._launch(s)
 
@@ -195,14 +222,19 @@ class Server:
         s.stream.synchronize()  # the handle's stream starts after the update
         o = P.opts_default(**self.opts_tmpl)
         o.seed = r.seed * 7919 + 1
+        o.warm_start = 1  # step 0: the Gaussian block drawn at admission
         if s.step > 0:
-            # warm start: previous subspace and bounds; eigenvalues move by at
-            # most ||eps E||_2 (Weyl), so the upper bound is widened by that
-            lo, mid, hi = s.bounds
-            shift = 4.0 * r.eps * math.sqrt(2.0)
-            o.warm_start = 1
+            # warm start: the previous subspace and bounds widened by a bound
+            # on ||eps E||_2 (eigenvalues move by at most that, Weyl); the
+            # Gaussian E of the perturbation has ||E||_2 close to sqrt(2),
+            # taken four times over
             o.have_bounds = 1
-            o.lambda_1, o.lambda_l, o.lambda_max = lo - shift, mid, hi + shift
+            o.lambda_1, o.lambda_l, o.lambda_max = P.chase_sequence_bounds(
+                s.bounds, 4.0 * r.eps * math.sqrt(2.0))
+        if self.capture:
+            V0 = np.ascontiguousarray(s.evecs.T.cpu().numpy()).T
+            r.captured.append([V0, (o.lambda_1, o.lambda_l, o.lambda_max)
+                               if s.step > 0 else None])
         s.pending = s.handle.solve_async(s.Hk, r.nev, r.nex, self.degree, self.tol, s.evecs, o)
         s.t_step = time.perf_counter()
 
@@ -216,6 +248,9 @@ class Server:
         r.resid.append(resid.copy())
         r.infos.append(inf)
         r.status.append(status)
+        if self.capture and r.captured[-1][1] is None:
+            # the first problem's bounds came from the library's Lanczos runs
+            r.captured[-1][1] = (inf["lambda_1"], inf["lambda_l"], inf["lambda_max"])
         # bounds for the next problem: lowest and largest Ritz values of the
         # search space and the upper bound of this one
         s.bounds = (float(evals[0]), float(inf["ritz_max"]), float(inf["lambda_max"]))

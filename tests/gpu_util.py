@@ -34,3 +34,12 @@ def col_rel_err(A, B):
     num = np.max(np.abs(A - B), axis=0)
     den = np.maximum(np.max(np.abs(B), axis=0), 1e-300)
     return float(np.max(num / den))
+
+
+def eig_rel_err(got, ref):
+    """max_i |got_i - ref_i| / |ref_i|: the error of every eigenvalue relative
+    to itself (the wanted eigenvalues of the test spectra are bounded away
+    from zero)."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    return float(np.max(np.abs(got - ref) / np.abs(ref)))

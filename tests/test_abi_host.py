@@ -39,7 +39,7 @@ def test_header_declares_entry_points():
                  "chase_log_cond_estimate", "chase_select_qr", "chase_degrees",
                  "chase_handle_create", "chase_solve_async", "chase_handle_query",
                  "chase_handle_wait", "chase_handle_destroy", "chase_workspace_bytes",
-                 "chase_strerror", "chase_last_error"]:
+                 "chase_sequence_bounds", "chase_strerror", "chase_last_error"]:
         assert must in names
 
 
@@ -177,7 +177,7 @@ def test_step_calls_reject_unknown_dtype_without_gpu(pkg):
         "filter": lambda dt, pr=pkg.PREC_FP64: pkg.lib.chase_filter(
             dt, pr, p, 10, 10, p, 10, 2, deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
             0.0, 1.0, -2.0, p, 10, None),
-        "qr": lambda dt: pkg.lib.chase_qr_factor(dt, p, 10, 10, 2, 2, ctypes.byref(fl), None),
+        "qr": lambda dt: pkg.lib.chase_qr_factor(dt, p, 10, 10, 2, 2, ctypes.byref(fl), dp, None),
         "rr": lambda dt: pkg.lib.chase_rayleigh_ritz(dt, p, 10, 10, p, 10, 2, dp, p, 10, p, 10,
                                                      None),
         "resid": lambda dt: pkg.lib.chase_residuals(dt, p, 10, p, 10, 10, 2, dp, dp, None),
@@ -190,3 +190,27 @@ def test_step_calls_reject_unknown_dtype_without_gpu(pkg):
     for bad in (2, -1):
         assert calls["filter"](pkg.REAL64, bad) == pkg.CHASE_EINVAL
         assert b"precision" in pkg.lib.chase_last_error()
+
+
+def test_sequence_bounds_widen_by_delta(pkg):
+    """Warm start of a perturbed problem: every eigenvalue of H + D lies
+    within ||D||_2 of one of H (Weyl), so the interval widens by delta on
+    both ends; lambda_l (an estimate, not a bound) is kept."""
+    lo, mid, hi = pkg.chase_sequence_bounds((-2.0, 10.0, 50.0), 0.25)
+    assert (lo, mid, hi) == (-2.25, 10.0, 50.25)
+    for bad in [((-2.0, 10.0, 50.0), -1e-3), ((1.0, 0.0, 2.0), 0.1), ((0.0, 2.0, 2.0), 0.1),
+                ((0.0, 1.0, float("nan")), 0.1)]:
+        with pytest.raises(pkg.ChaseError):
+            pkg.chase_sequence_bounds(*bad)
+    # Weyl on an explicit case: symmetric H and D with ||D||_2 = delta
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((60, 60))
+    H = 0.5 * (A + A.T)
+    B = rng.standard_normal((60, 60))
+    D = 0.5 * (B + B.T)
+    delta = float(np.linalg.norm(D, 2)) * 1e-3
+    D = D * (delta / np.linalg.norm(D, 2))
+    w = np.linalg.eigvalsh(H)
+    w2 = np.linalg.eigvalsh(H + D)
+    lo, mid, hi = pkg.chase_sequence_bounds((w[0], w[20], w[-1]), delta)
+    assert lo <= w2[0] and w2[-1] <= hi

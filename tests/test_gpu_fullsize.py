@@ -60,6 +60,8 @@ def test_solve_full_size(problem, H_host, gpu):
     assert out["status"] == P.CHASE_OK
     scale = np.max(np.abs(lam))
     assert np.max(np.abs(out["evals"] - lam[:NEV])) <= 1e-10 * scale
+    # each eigenvalue relative to itself (the wanted ones lie in [-2, -1])
+    assert np.max(np.abs(out["evals"] - lam[:NEV]) / np.abs(lam[:NEV])) <= 1e-10
     assert np.all(out["resid"] < 1e-10)
     # residuals of sampled pairs recomputed by the oracle's definition
     cols = [0, 1, 250, 499, 998, 999]
@@ -85,6 +87,7 @@ def test_mixed_precision_full_size_n30000(gpu):
     assert out["status"] == P.CHASE_OK
     assert out["info"]["filter_fp32_iters"] >= 1
     assert np.max(np.abs(out["evals"] - lam[:1500])) <= 1e-10 * np.max(np.abs(lam))
+    assert np.max(np.abs(out["evals"] - lam[:1500]) / np.abs(lam[:1500])) <= 1e-10
     assert np.all(out["resid"] < 1e-10)
     del H
     torch.cuda.empty_cache()
@@ -104,6 +107,7 @@ def test_real_solve_large(gpu, N, nev, nex, fam):
     torch.cuda.synchronize()
     assert out["status"] == P.CHASE_OK
     assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10 * np.max(np.abs(lam))
+    assert np.max(np.abs(out["evals"] - lam[:nev]) / np.abs(lam[:nev])) <= 1e-10
     assert np.all(out["resid"] < 1e-10)
     del H
     torch.cuda.empty_cache()

@@ -1,7 +1,10 @@
 """Serving form: continuous batching of correlated eigenproblem sequences on
 asynchronous handles.  Each result must be the same alone and in the mix;
-eigenvalues are checked against a CPU full diagonalisation of every H_j; the
-scheduler must never admit beyond its HBM budget."""
+eigenvalues are checked against a CPU full diagonalisation of every H_j and,
+step by step, against the oracle's solve of the same H_j from the same
+(warm) start block and bounds; the scheduler must never admit beyond its HBM
+budget, and a request that fits may overtake one that does not only a
+bounded number of times."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -75,3 +78,68 @@ def test_admission_respects_hbm_budget(gpu):
     for a, b in zip(order, order[1:]):
         assert b.t_admit >= a.t_done - 1e-6
     assert all(all(st == 0 for st in r.status) for r in done)
+
+
+def test_warm_started_steps_match_oracle(gpu):
+    """Two small sequences, every step against the oracle: the server keeps
+    a host copy of each step's start block (the Gaussian block of step 0,
+    the previous step's subspace afterwards) and bounds (step 0: the
+    library's Lanczos bounds; afterwards the previous ones widened by the
+    perturbation bound), and the oracle solves the same H_j from them (Alg. 1
+    with its optional start block and bounds, the warm start of Sec. 1.2).
+    The server filters in FP32, the oracle in FP64: eigenvalues agree to
+    1e-10 and iteration counts to within one."""
+    import torch
+    from paper_2603_10514_amd import serve
+    from oracle import solver as osolver
+    reqs = _requests(gpu, [360, 520], steps=3)
+    srv = serve.Server(n_slots=2, N_max=600, device=gpu, capture=True)
+    done = srv.run(reqs)
+    srv.close()
+    for r in done:
+        assert len(r.captured) == r.steps
+        H = r.H0.clone()
+        scale = float(np.max(np.abs(r.lam)))
+        for j in range(r.steps):
+            if j > 0:
+                H += serve.perturbation(r.N, r.seed, j, r.eps, H.dtype, gpu)
+            torch.cuda.synchronize()
+            Hn = np.ascontiguousarray(H.T.cpu().numpy()).T
+            V0, b = r.captured[j]
+            print("serve oracle case rid %d N %d step %d bounds %s" % (r.rid, r.N, j, b), flush=True)
+            ref = osolver.chase_solve(Hn, r.nev, r.nex, 20, 1e-10, V0=V0, bounds=b, min_deg=10,
+                                      max_deg=36)
+            assert ref.converged == r.nev and r.status[j] == 0
+            assert np.max(np.abs(r.evals[j] - ref.evals)) <= 1e-10 * scale, (r.rid, j)
+            assert np.max(np.abs(r.evals[j] - ref.evals) / np.abs(ref.evals)) <= 1e-10
+            assert abs(r.infos[j]["iters"] - ref.iters) <= 1, (r.infos[j]["iters"], ref.iters)
+            if j > 0:  # warm steps start from the previous subspace and bounds
+                assert b[0] < r.evals[j][0] and b[2] > b[1]
+
+
+def test_bypass_admission_is_bounded(gpu):
+    """A large request that does not fit next to a running one is overtaken
+    by smaller ones at most max_bypass times; then it is admitted before
+    any later request, as soon as the memory frees up."""
+    from paper_2603_10514_amd import serve
+    Ns = [700, 880, 400, 420, 440, 460, 480]
+    reqs = _requests(gpu, Ns, steps=1, arrival_gap=0.0)
+    big = serve.data_bytes(880, *serve.request_shape(880))
+    first = serve.data_bytes(700, *serve.request_shape(700))
+    small = max(serve.data_bytes(n, *serve.request_shape(n)) for n in Ns[2:])
+    # the 880 request fits only alone; the small ones fit beside the 700 one
+    budget = max(big, first + small) + small // 2
+    assert first + big > budget
+    srv = serve.Server(n_slots=2, N_max=900, hbm_budget=budget, device=gpu, max_bypass=2)
+    done = srv.run(reqs)
+    srv.close()
+    assert srv.peak_used <= srv.budget
+    assert all(all(st == 0 for st in r.status) for r in done)
+    by_rid = {r.rid: r for r in done}
+    big_req = by_rid[1]
+    assert big_req.bypassed <= 2
+    overtook = [r for r in done if r.rid > 1 and r.t_admit < big_req.t_admit]
+    assert len(overtook) == big_req.bypassed
+    # nothing that arrived after it was admitted once its bypass budget ran out
+    later = [r for r in done if r.rid > 1 and r.t_admit > big_req.t_admit]
+    assert len(overtook) + len(later) == len(Ns) - 2

@@ -7,7 +7,7 @@ import pytest
 import synth
 from oracle import solver as osolver
 
-from gpu_util import to_dev, to_host
+from gpu_util import eig_rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,9 @@ def test_config_small_real_matches_oracle(P, gpu):
     scale = np.max(np.abs(lam))
     assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10 * scale
     assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10 * scale
+    # each eigenvalue relative to itself (all wanted ones lie near -1)
+    assert eig_rel_err(out["evals"], ref.evals) <= 1e-10
+    assert eig_rel_err(out["evals"], lam[:nev]) <= 1e-10
     assert np.all(out["resid"] < 1e-10)
     # same history: iterations, QR choice per iteration, locking
     assert out["info"]["iters"] == ref.iters
@@ -65,6 +68,7 @@ def test_complex_dft_family_matches_oracle(P, gpu):
     scale = np.max(np.abs(lam))
     assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-10 * scale
     assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10 * scale
+    assert eig_rel_err(out["evals"], ref.evals) <= 1e-10  # wanted ones in [-2, -1]
     assert np.all(out["resid"] < 1e-10)
     assert out["info"]["iters"] == ref.iters
 
@@ -146,6 +150,7 @@ def test_mixed_precision_matches_fp64_oracle(P, gpu, cplx, family):
     assert out["status"] == P.CHASE_OK
     scale = np.max(np.abs(lam))
     assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-10 * scale
+    assert eig_rel_err(out["evals"], ref.evals) <= 1e-10
     assert np.all(out["resid"] < 1e-10)
     assert out["info"]["filter_fp32_iters"] >= 1
     assert out["log"][0]["filter_prec"] == P.PREC_MIXED
@@ -190,11 +195,17 @@ def test_exact_condition_number_logged(P, gpu):
         assert g["cond_est"] >= g["cond_exact"]
 
 
-@pytest.mark.parametrize("degree", [6, 40, 70, 100])
+@pytest.mark.parametrize("degree", [6, 40, 70, 100, 120, 166, 200])
 def test_fixed_degree_sweep_exercises_alg3(P, gpu, degree):
     """Without degree optimisation the first iteration's estimate grows with
-    the degree and walks Alg. 3 through CholeskyQR, CholeskyQR2 and the
-    shifted branch (stress spectrum, scaled down to N = 1500)."""
+    the degree and walks Alg. 3 through CholeskyQR, CholeskyQR2, the shifted
+    branch and, from degree 120 on (exact kappa_2 above 1e14), the
+    Householder fallback reached through the estimate path: the shifted pass
+    succeeds and the CholeskyQR2 after it fails (stress spectrum, scaled down
+    to N = 1500).  At degree 120 the outcome sits at the edge of the shifted
+    branch's range (rounding-level perturbations of the block flip it in the
+    oracle), so only the branch and the estimate are compared there; from 166
+    on the failure is certain and must match."""
     N, nev, nex = 1500, 60, 30
     H, lam = synth.planted_numpy(N, "stress", 25, n_low=60)
     V0 = synth.start_block(N, nev + nex, 26)
@@ -205,12 +216,26 @@ def test_fixed_degree_sweep_exercises_alg3(P, gpu, degree):
                         warm_start=1, have_bounds=1, lambda_1=b[0], lambda_l=b[1],
                         lambda_max=b[2], deg_opt=0, max_iter=3, exact_cond=True)
     g, o = out["log"][0], ref.log[0]
-    assert g["variant"] == o["variant"]
+    print("degree %d: est %.3e exact %.3e (oracle %.3e) branch %s chol_failed gpu %d oracle %d"
+          % (degree, g["cond_est"], g["cond_exact"], o["cond_exact"], o["variant"],
+             g["chol_failed"], o["chol_failed"]), flush=True)
     assert g["cond_est"] == pytest.approx(o["cond_est"], rel=1e-9)
     assert g["cond_est"] >= g["cond_exact"]
-    assert g["cond_exact"] == pytest.approx(o["cond_exact"], rel=1e-2)
+    if o["cond_exact"] < 1e12:  # above, the SVD's smallest value is rounding noise
+        assert g["cond_exact"] == pytest.approx(o["cond_exact"], rel=1e-2)
     expect = "chol1" if o["cond_est"] < 20 else ("chol2" if o["cond_est"] <= 1e8 else "shifted")
-    assert g["variant"] == expect
+    assert o["variant"] == expect
+    if expect == "shifted":
+        # the shift the library added, against the oracle's (Alg. 3)
+        assert g["qr_shift"] == pytest.approx(o["qr_shift"], rel=1e-10, abs=0)
+    if degree >= 166:
+        assert o["chol_failed"] and g["chol_failed"] == 1
+    if degree != 120:
+        assert bool(g["chol_failed"]) == o["chol_failed"]
+    assert g["variant"] == ("householder" if g["chol_failed"] else expect)
+    # the fallback keeps the iteration going: every iteration's block is
+    # orthonormalised and the history matches the oracle's afterwards
+    assert len(out["log"]) == len(ref.log)
 
 
 def _planted_with_multiplicity(N, mult, seed):

@@ -98,5 +98,39 @@ def test_shift_scales_with_frobenius_norm_squared():
     X = planted_block(200, 10, 10.0, 7)
     s1 = qr.shift_value(X)
     s2 = qr.shift_value(3.0 * X)
-    assert s2 == pytest.approx(9.0 * s1, rel=1e-13)
+    assert s2 == pytest.approx(9.0 * s1, rel=1e-13, abs=0)
     assert 0 < s1 < 1e-9
+
+
+def test_shift_hand_evaluated():
+    """Alg. 3's shift s = 11 (m n + n (n + 1)) u ||X||^2 (reading: m rows,
+    n columns, u = 2^-53, squared Frobenius norm), evaluated by hand on
+    X = [e_1, 2 e_2] in R^{4 x 2}: m n = 8, n (n + 1) = 6, ||X||_F^2 = 1 + 4 = 5,
+    so s = 11 * 14 * 5 * 2^-53 = 770 * 2^-53.  A slip in any factor (the 11,
+    u = 2^-52, n (n - 1), m (m + 1), an unsquared norm, a stray scale) changes
+    the value by far more than the tolerance."""
+    X = np.zeros((4, 2))
+    X[0, 0] = 1.0
+    X[1, 1] = 2.0
+    assert qr.shift_value(X) == pytest.approx(8.548717289613705e-14, rel=1e-15, abs=0)
+    assert 770.0 * 2.0 ** -53 == pytest.approx(8.548717289613705e-14, rel=1e-15, abs=0)
+    # complex entries: |x|^2 enters the norm (||X||_F^2 = 1 + |1 + 2i|^2 = 6)
+    Xc = np.zeros((3, 1), dtype=complex)
+    Xc[0, 0] = 1.0
+    Xc[2, 0] = 1.0 + 2.0j
+    # m n = 3, n (n + 1) = 2: s = 11 * 5 * 6 * 2^-53 = 330 * 2^-53
+    assert qr.shift_value(Xc) == pytest.approx(330.0 * 2.0 ** -53, rel=1e-15, abs=0)
+
+
+def test_shifted_pass_adds_the_shift_to_the_gram_diagonal():
+    """The shifted pass factors X^H X + s I: on X = [e_1, 2 e_2] that matrix is
+    diag(1 + s, 4 + s), so R = diag(sqrt(1 + s), sqrt(4 + s)) and the
+    output columns are e_1 / sqrt(1 + s) and 2 e_2 / sqrt(4 + s)."""
+    X = np.zeros((4, 2))
+    X[0, 0] = 1.0
+    X[1, 1] = 2.0
+    s = 770.0 * 2.0 ** -53
+    Q = qr.shifted_cholqr_pass(X)
+    assert Q[0, 0] == pytest.approx(1.0 / np.sqrt(1.0 + s), rel=1e-16, abs=0)
+    assert Q[1, 1] == pytest.approx(2.0 / np.sqrt(4.0 + s), rel=1e-16, abs=0)
+    assert 1.0 - Q[0, 0] == pytest.approx(0.5 * s, rel=1e-2, abs=0)
