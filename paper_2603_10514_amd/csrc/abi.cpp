@@ -254,13 +254,11 @@ chase_status chase_filter(chase_dtype dtype, chase_precision prec, const void *H
     cx.stream = stream ? (hipStream_t)stream : own;
     Work &w = cx.w;
     std::vector<int> d(deg, deg + ncols);
-    CHASE_HIP(hipMemcpyAsync(w.deg, d.data(), 4 * (size_t)ncols, hipMemcpyHostToDevice,
-                             cx.stream));
     gather_cols(cplx, f32, V, ldv, w.X0, N, (int)N, ncols, nullptr, cx.stream);
     if (f32) convert_to32(cplx, H, ldh, w.H32, N, (int)N, (int)N, cx.stream);
     void *bufs[3] = {w.X0, w.B1, w.B2};
-    filter(cx, cplx, f32, f32 ? w.H32 : H, f32 ? N : ldh, N, bufs, N, ncols, w.deg, d, c, e,
-           gamma, out, ldo);
+    filter(cx, cplx, f32, f32 ? w.H32 : H, f32 ? N : ldh, N, bufs, N, ncols, d, c, e, gamma, out,
+           ldo);
     hipError_t err = hipStreamSynchronize(cx.stream);
     cx.stream = own;
     if (err != hipSuccess) {

@@ -32,8 +32,10 @@
 //              splits, split s writes C + s * split_stride.
 //  EPI_FILTER  one step of the sigma-scaled Chebyshev recurrence (Alg. 4):
 //              out = alpha * (acc - shift * Xcur) + beta * Xprev, where Xcur is
-//              B itself (K == M); column j goes to Ofinal when deg[j] == step
-//              (its last step, Sec. 2.2) and to Onext otherwise.
+//              B itself (K == M); the columns are sorted by ascending degree,
+//              so those whose degree equals this step (their last step,
+//              Sec. 2.2) are the global columns below final_end: they go to
+//              Ofinal, the others to Onext.
 #pragma once
 #include <type_traits>
 
@@ -101,7 +103,7 @@ struct GemmArgs {
   const void *Xprev; int64_t ldp;
   void *Onext; int64_t ldn;
   void *Ofinal; int64_t ldf;
-  const int *deg; int step;
+  int final_end;          // EPI_FILTER: global columns < final_end are final
   const int *flag;       // non-null and *flag != 0: the launch does nothing
   // remainder split (set by the launcher): this launch covers logical tiles
   // [tile0, tile0 + ntiles) (ntiles == 0: all); with Pk set, every (tile,
@@ -158,7 +160,7 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &p, int i, int j, 
       vr += beta * mre(xp);
       vi += beta * mim(xp);
     }
-    if (p.deg[jg] == p.step)
+    if (jg < p.final_end)
       ((GEF *)p.Ofinal)[(int64_t)jg * p.ldf + i] = mmake<EF, FT>((FT)vr, (FT)vi);
     else
       ((GEw *)p.Onext)[(int64_t)jg * p.ldn + i] = mmake<E, T>(vr, vi);

@@ -192,7 +192,7 @@ static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int 
       al(es * (size_t)ns * L * L),                                     // P
       al(es * L * L), al(es * L * L), al(es * L * L), al(es * L * L), al(es * L * L),  // G R Ri T A
       al(8 * (size_t)L), al(8 * (size_t)L), al(8 * (size_t)L), al(64),  // theta resid E trace
-      al(16), al(4 * (size_t)L), al(4 * (size_t)L), al(16),              // flag deg perm rinfo
+      al(16), al(4 * (size_t)L), al(16),                                 // flag perm rinfo
       al(es * L),                                                         // tau
       mixed ? al(es / 2 * (size_t)N * N) : 0,                             // H32
       k ? al(es * (size_t)N * (k + 1) * nv) : 0,                          // LV
@@ -277,7 +277,7 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int
   w.A = b + lo.off[i++];
   w.theta = (double *)(b + lo.off[i++]); w.resid = (double *)(b + lo.off[i++]);
   w.E = (double *)(b + lo.off[i++]); w.trace = (double *)(b + lo.off[i++]);
-  w.flag = (int *)(b + lo.off[i++]); w.deg = (int *)(b + lo.off[i++]);
+  w.flag = (int *)(b + lo.off[i++]);
   w.perm = (int *)(b + lo.off[i++]); w.rinfo = (int *)(b + lo.off[i++]);
   w.tau = b + lo.off[i++];
   w.H32 = mixed ? (void *)(b + lo.off[i]) : nullptr; i++;
@@ -299,7 +299,6 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int
     CHASE_HIP(hipHostMalloc((void **)&w.h_flag, 16));
     CHASE_HIP(hipHostMalloc((void **)&w.h_aux, 32));
     CHASE_HIP(hipHostMalloc((void **)&w.h_perm, 4 * (size_t)h_cap_L));
-    CHASE_HIP(hipHostMalloc((void **)&w.h_deg, 4 * (size_t)h_cap_L));
   }
 }
 
@@ -310,9 +309,8 @@ void Ctx::free_pinned() {
   if (w.h_flag) (void)hipHostFree(w.h_flag);
   if (w.h_aux) (void)hipHostFree(w.h_aux);
   if (w.h_perm) (void)hipHostFree(w.h_perm);
-  if (w.h_deg) (void)hipHostFree(w.h_deg);
   w.h_theta = w.h_resid = w.h_ab = w.h_aux = nullptr;
-  w.h_flag = w.h_perm = w.h_deg = nullptr;
+  w.h_flag = w.h_perm = nullptr;
   h_cap_L = h_cap_lz = 0;
 }
 
@@ -352,36 +350,64 @@ static GemmArgs bigargs(Ctx &c) {
 }
 
 // Alg. 4 with per-vector degrees: one filter-GEMM launch per degree step,
-// each on the active suffix of the degree-sorted block.
-int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, void *bufs[3],
-           int64_t ldb, int ncols, const int *deg_dev, const std::vector<int> &deg_sorted,
-           double cc, double e, double gamma, void *out, int64_t ldo) {
+// each on the active suffix of the degree-sorted block.  V (read only
+// unless it is one of bufs) holds the input columns; the steps' outputs
+// rotate through the three buffers: step 1 reads V and writes bufs[0],
+// step 2 reads bufs[0] (previous V) and writes bufs[1], step i >= 3 reads
+// bufs[(i - 2) % 3] (previous bufs[(i - 3) % 3]) and writes
+// bufs[(i - 1) % 3].  Passing V == bufs[2] makes it a ring of three buffers.
+// Column a's last step (degree m_a) writes out[:, a] instead.
+int filter_enqueue(hipStream_t st, void *tail_ws, size_t tail_bytes, bool cplx, bool f32,
+                   const void *H, int64_t ldh, int64_t N, const void *V, int64_t ldv,
+                   void *const bufs[3], int64_t ldb, int ncols, const int *deg_sorted, double cc,
+                   double e, double gamma, void *out, int64_t ldo) {
   if (ncols <= 0) return 0;
   const double sigma1 = e / (gamma - cc);
   double s = sigma1, sprev = 0.0;
-  const int mmax = deg_sorted.back();
+  const int mmax = deg_sorted[ncols - 1];
   int launches = 0;
+  auto first_at_least = [&](int d) {
+    return (int)(std::lower_bound(deg_sorted, deg_sorted + ncols, d) - deg_sorted);
+  };
   for (int step = 1; step <= mmax; ++step) {
-    const int start =
-        (int)(std::lower_bound(deg_sorted.begin(), deg_sorted.end(), step) - deg_sorted.begin());
-    GemmArgs a = bigargs(c);
+    const int start = first_at_least(step);
+    GemmArgs a = gargs();
+    a.tail_ws = tail_ws;
+    a.tail_ws_bytes = tail_bytes;
     a.A = H; a.lda = ldh;
-    a.B = bufs[(step - 1) % 3]; a.ldb = ldb;
+    if (step == 1) {
+      a.B = V; a.ldb = ldv;
+    } else {
+      a.B = bufs[(step - 2) % 3]; a.ldb = ldb;
+    }
     a.M = (int)N; a.N = ncols - start; a.K = (int)N;
     a.col0 = start;
     a.alpha = (step == 1 ? 1.0 : 2.0) * s / e;
     a.beta = step == 1 ? 0.0 : -sprev * s;
     a.shift = cc;
-    a.Xprev = bufs[(step + 1) % 3]; a.ldp = ldb;
-    a.Onext = bufs[step % 3]; a.ldn = ldb;
+    if (step == 2) {
+      a.Xprev = V; a.ldp = ldv;
+    } else if (step > 2) {
+      a.Xprev = bufs[(step - 3) % 3]; a.ldp = ldb;
+    }
+    a.Onext = bufs[(step - 1) % 3]; a.ldn = ldb;
     a.Ofinal = out; a.ldf = ldo;
-    a.deg = deg_dev; a.step = step;
-    launches += gemm(cplx, f32, true, true, true, GEMM_BIG, a, 1, c.stream);
+    a.final_end = first_at_least(step + 1);
+    launches += gemm(cplx, f32, true, true, true, GEMM_BIG, a, 1, st);
     sprev = s;
     s = 1.0 / (2.0 / sigma1 - s);
   }
   CHASE_HIP(hipGetLastError());
   return launches;
+}
+
+int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, void *bufs[3],
+           int64_t ldb, int ncols, const std::vector<int> &deg_sorted, double cc, double e,
+           double gamma, void *out, int64_t ldo) {
+  // bufs[0] holds the input; it is the ring's third buffer
+  void *const ring[3] = {bufs[1], bufs[2], bufs[0]};
+  return filter_enqueue(c.stream, c.w.SK, c.w.sk_bytes, cplx, f32, H, ldh, N, bufs[0], ldb, ring,
+                        ldb, ncols, deg_sorted.data(), cc, e, gamma, out, ldo);
 }
 
 // Tile shape of the K-split products X^H Y (Gram matrices, V^H C).
@@ -855,28 +881,26 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     auto by_degree = [&](int a, int b) { return m[a] < m[b]; };
     std::stable_sort(order.begin(), order.begin() + nW, by_degree);
     std::stable_sort(order.begin() + nW, order.end(), by_degree);
-    // permutation and degrees go up from their own pinned mirrors, which the
-    // host rewrites only after the next end-of-iteration synchronisation
+    // the permutation goes up from its own pinned mirror, which the host
+    // rewrites only after the next end-of-iteration synchronisation
     std::vector<int> msorted(Lp);
     for (int a = 0; a < Lp; ++a) {
       msorted[a] = m[order[a]];
       w.h_perm[a] = order[a] + k;
-      w.h_deg[a] = msorted[a];
     }
     CHASE_HIP(hipMemcpyAsync(w.perm, w.h_perm, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
-    CHASE_HIP(hipMemcpyAsync(w.deg, w.h_deg, 4 * (size_t)Lp, hipMemcpyHostToDevice, s));
     void *bufs[3] = {w.X0, w.B1, w.B2};
     gather_cols(cplx, f32, evecs, ldv, w.X0, N, (int)N, nW, w.perm, s);
     CHASE_HIP(hipEventRecord(c.ev[0], s));
     const std::vector<int> msW(msorted.begin(), msorted.begin() + nW);
-    int nl = filter(c, cplx, f32, f32 ? w.H32 : H, f32 ? N : ldh, N, bufs, N, nW, w.deg, msW, cc,
+    int nl = filter(c, cplx, f32, f32 ? w.H32 : H, f32 ? N : ldh, N, bufs, N, nW, msW, cc,
                     e, gamma, (char *)w.Xq + es * (size_t)k * N, N);
     CHASE_HIP(hipEventRecord(c.ev[5], s));
     int64_t mv32 = 0;
     if (nW < Lp) {  // the buffer columns through the FP32 filter
       const std::vector<int> msB(msorted.begin() + nW, msorted.end());
       gather_cols(cplx, true, evecs, ldv, w.X0, N, (int)N, Lp - nW, w.perm + nW, s);
-      nl += filter(c, cplx, true, w.H32, N, N, bufs, N, Lp - nW, w.deg + nW, msB, cc, e, gamma,
+      nl += filter(c, cplx, true, w.H32, N, N, bufs, N, Lp - nW, msB, cc, e, gamma,
                    (char *)w.Xq + es * (size_t)(k + nW) * N, N);
       for (int v : msB) mv32 += v;
     }

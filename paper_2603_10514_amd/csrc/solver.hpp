@@ -21,7 +21,7 @@ struct Work {
   void *P = nullptr;                                                  // nsplit x L x L
   void *G = nullptr, *R = nullptr, *Ri = nullptr, *T = nullptr, *A = nullptr;  // L x L
   double *theta = nullptr, *resid = nullptr, *E = nullptr, *trace = nullptr;
-  int *flag = nullptr, *deg = nullptr, *perm = nullptr, *rinfo = nullptr;
+  int *flag = nullptr, *perm = nullptr, *rinfo = nullptr;
   void *tau = nullptr;
   void *H32 = nullptr;                                  // N x N in FP32 (mixed)
   void *LV = nullptr, *LW = nullptr, *Lh = nullptr, *LhP = nullptr;  // Lanczos runs
@@ -33,7 +33,7 @@ struct Work {
   double *h_theta = nullptr, *h_resid = nullptr, *h_ab = nullptr;
   double *h_aux = nullptr;  // [0] ||X||_F^2, [1] shift of the last shifted pass
   int *h_flag = nullptr;    // [0..1] QR failure flag, [2] eigensolver info
-  int *h_perm = nullptr, *h_deg = nullptr;
+  int *h_perm = nullptr;
 };
 
 size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec);
@@ -69,9 +69,18 @@ void lanczos_bounds_from_runs(const std::vector<double> &alpha, const std::vecto
                               int nvec, int64_t N, int nsearch, double bounds[3]);
 
 // Steps (device buffers; enqueue on ctx.stream).
+// Alg. 4 on explicit buffers (no context): V is the input block, bufs the
+// three rotating step buffers (V may be bufs[2]), tail_ws the remainder
+// split's scratch (may be null: no split).  Returns the GEMM dispatches.
+int filter_enqueue(hipStream_t st, void *tail_ws, size_t tail_bytes, bool cplx, bool f32,
+                   const void *H, int64_t ldh, int64_t N, const void *V, int64_t ldv,
+                   void *const bufs[3], int64_t ldb, int ncols, const int *deg_sorted, double cc,
+                   double e, double gamma, void *out, int64_t ldo);
+// The same on the context's buffers: bufs[0] holds the input, bufs[1..2] and
+// bufs[0] rotate.
 int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, void *bufs[3],
-           int64_t ldb, int ncols, const int *deg_dev, const std::vector<int> &deg_sorted,
-           double cc, double e, double gamma, void *out, int64_t ldo);
+           int64_t ldb, int ncols, const std::vector<int> &deg_sorted, double cc, double e,
+           double gamma, void *out, int64_t ldo);
 struct QrOut {
   void *Q;          // buffer that holds Q
   bool failed;      // a Cholesky failed and the Householder QR ran instead
