@@ -212,6 +212,29 @@ chase_status chase_filter(chase_dtype dtype, chase_precision prec, const void *H
                           const int32_t *degrees, double c, double e, double gamma,
                           void *out, int64_t ldo, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * filter as chase_filter in FP64 (dtype REAL64 or COMPLEX128), with every
+ * buffer beyond the inputs and outputs in a static device array of
+ * CHASE_FILTER_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it
+ * runs on until the process ends: the three step buffers (N x ncols each)
+ * and the partial tiles of the GEMM's remainder split.  The call allocates
+ * nothing, does not synchronise and returns once the work is enqueued on
+ * `stream` (NULL: the default stream); `out` is valid when the stream has
+ * reached that point.  H, V, out and degrees as for chase_filter (degrees
+ * on the host, read during the call).
+ * Limits and errors: EINVAL when 3 N ncols times the element size (8 or 16
+ * bytes) exceeds CHASE_FILTER_NOALLOC_SCRATCH_BYTES (each buffer rounded up
+ * to 256 bytes), and for the argument errors of chase_filter; EDEVICE if a
+ * launch fails.  Every call on one GPU uses that GPU's one array, so calls
+ * that overlap in time on the same GPU (on different streams or host
+ * threads) race and must be serialised by the caller. */
+#define CHASE_FILTER_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+chase_status chase_filter_noalloc(chase_dtype dtype, const void *H, int64_t N, int64_t ldh,
+                                  const void *V, int64_t ldv, int32_t ncols,
+                                  const int32_t *degrees, double c, double e, double gamma,
+                                  void *out, int64_t ldo, void *stream);
+
 /* ln of estimate (1.2): m_next ln|rho(theta_next)| + (m_max - m_next) ln|rho(lam1)|
  * (eta = 1); |rho(x)| = |t| + sqrt(t^2 - 1) for |t| = |x - c|/e > 1, else 1. */
 double chase_log_cond_estimate(double theta_next, int32_t m_next, int32_t m_max, double lam1,

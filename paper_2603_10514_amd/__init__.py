@@ -108,6 +108,9 @@ _sig("chase_handle_wait", ctypes.c_int, [_p])
 _sig("chase_handle_destroy", None, [_p])
 _sig("chase_filter", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _p, _i64, _i64, _p, _i64, _i32,
                                     _ip, _d, _d, _d, _p, _i64, _p])
+_sig("chase_filter_noalloc", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i64, _i32, _ip, _d,
+                                            _d, _d, _p, _i64, _p])
+FILTER_NOALLOC_SCRATCH_BYTES = 64 << 20  # CHASE_FILTER_NOALLOC_SCRATCH_BYTES
 _sig("chase_log_cond_estimate", _d, [_d, _i32, _i32, _d, _d, _d])
 _sig("chase_select_qr", ctypes.c_int, [_d, _d, _d])
 _sig("chase_degrees", None, [_dp, _dp, _i32, _d, _d, _d, _i32, _i32, _i32, _ip])
@@ -288,6 +291,22 @@ def chase_filter(H, V, degrees, c, e, gamma, out=None, precision=PREC_FP64, stre
     st = lib.chase_filter(_dtype_code(H), precision, hp, N, ldh, vp, ldv, int(deg.size),
                           deg.ctypes.data_as(_ip), c, e, gamma, op, ldo, _stream_ptr(stream))
     _check(st, "chase_filter")
+    return out
+
+
+def chase_filter_noalloc(H, V, degrees, c, e, gamma, out, stream=None):
+    """chase_filter (FP64) on the library's static scratch: nothing is
+    allocated by the library; `out` must be given.  Asynchronous: the
+    result is valid once the stream has reached this call's work."""
+    N = H.shape[0]
+    deg = np.ascontiguousarray(np.asarray(degrees, dtype=np.int32))
+    hp, ldh = _hermitian_ptr(H)
+    vp, ldv = _colmajor(V, "V")
+    op, ldo = _colmajor(out, "out")
+    st = lib.chase_filter_noalloc(_dtype_code(H), hp, N, ldh, vp, ldv, int(deg.size),
+                                  deg.ctypes.data_as(_ip), c, e, gamma, op, ldo,
+                                  _stream_ptr(stream))
+    _check(st, "chase_filter_noalloc")
     return out
 
 

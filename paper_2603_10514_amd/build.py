@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchase.so")
-SOURCES = ["kernels.hip", "solver.cpp", "abi.cpp"]
+SOURCES = ["kernels.hip", "solver.cpp", "abi.cpp", "noalloc.cpp"]
 ARCH = os.environ.get("CHASE_OFFLOAD_ARCH", "gfx950")
 
 

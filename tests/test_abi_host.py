@@ -214,3 +214,26 @@ def test_sequence_bounds_widen_by_delta(pkg):
     w2 = np.linalg.eigvalsh(H + D)
     lo, mid, hi = pkg.chase_sequence_bounds((w[0], w[20], w[-1]), delta)
     assert lo <= w2[0] and w2[-1] <= hi
+
+
+def test_filter_noalloc_rejects_without_touching_the_device(pkg):
+    """Argument and size errors of the no-allocation filter are caught on the
+    host, before any device call (no GPU here)."""
+    p = ctypes.c_void_p(16)  # never dereferenced
+    deg = np.ones(4, dtype=np.int32)
+    dp = deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    f = pkg.lib.chase_filter_noalloc
+    assert f(2, p, 10, 10, p, 10, 4, dp, 0.0, 1.0, -2.0, p, 10, None) == pkg.CHASE_EINVAL
+    assert f(pkg.REAL64, p, 10, 10, p, 10, 11, dp, 0.0, 1.0, -2.0, p, 10, None) == pkg.CHASE_EINVAL
+    assert f(pkg.REAL64, p, 10, 10, p, 10, 4, dp, 0.0, 0.0, -2.0, p, 10, None) == pkg.CHASE_EINVAL
+    bad = np.array([1, 3, 2, 4], dtype=np.int32)
+    assert f(pkg.REAL64, p, 10, 10, p, 10, 4, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+             0.0, 1.0, -2.0, p, 10, None) == pkg.CHASE_EINVAL
+    # beyond the scratch: 3 N ncols 16 bytes > 64 MiB
+    N = 100000
+    ncols = 20
+    big = np.ones(ncols, dtype=np.int32)
+    assert f(pkg.COMPLEX128, p, N, N, p, N, ncols, big.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+             0.0, 1.0, -2.0, p, N, None) == pkg.CHASE_EINVAL
+    assert b"scratch" in pkg.lib.chase_last_error()
+    assert f(pkg.REAL64, p, 10, 10, p, 10, 0, dp, 0.0, 1.0, -2.0, p, 10, None) == pkg.CHASE_OK
