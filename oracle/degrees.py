@@ -2,9 +2,9 @@
 
 Oracle module (test infrastructure only).
 
-The paper says each vector is filtered with a degree "just high enough" to
-converge within the tolerance, with the initial degree 20 and a cap of 36 in
-its experiments, but gives no formula.  Pinned by a property, not by the
+Sec. 2.2 filters each vector with its own degree, chosen as the smallest
+one that brings that vector's residual to the tolerance, and Sec. 4.3 uses
+an initial degree of 20 and a cap of 36; no formula is given.  Pinned by a property, not by the
 paper (tests: the predicted degree brings a vector whose unwanted components
 lie in the damped interval to tol, and one degree fewer than the bare
 prediction does not); the margin of 2 is a reading.  The reading used here:

@@ -5,8 +5,8 @@
 (Run as a script: `python -m` would import the package, which loads the
 previous libchase.so.)
 
-Compiles every source under csrc/ with hipcc for gfx950 and links rocSOLVER
-and rocBLAS.  Always recompiles; the output lands next to this file."""
+Compiles every source under csrc/ with hipcc for gfx950 (no vendor math
+library is linked).  Always recompiles; the output lands next to this file."""
 import os
 import shutil
 import subprocess
@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchase.so")
-SOURCES = ["kernels.hip", "solver.cpp", "abi.cpp", "noalloc.cpp"]
+SOURCES = ["kernels.hip", "eig.hip", "solver.cpp", "abi.cpp", "noalloc.cpp"]
 ARCH = os.environ.get("CHASE_OFFLOAD_ARCH", "gfx950")
 
 
@@ -50,8 +50,7 @@ def build(verbose=False, jobs=3, defines=(), out=None):
             _drain(procs, verbose)
     _drain(procs, verbose)
     tmp = lib + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
-        "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     _run(cmd, verbose)
     os.replace(tmp, lib)
     return lib

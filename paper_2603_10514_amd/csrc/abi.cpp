@@ -130,17 +130,14 @@ chase_status chase_solve(const void *H, int64_t N, int64_t ldh, int32_t nev, int
     c.ensure_init();
     hipStream_t own = c.stream;
     if (opts->stream) c.stream = (hipStream_t)opts->stream;
-    c.set_stream(c.stream);
     chase_status r;
     try {
       r = solve(c, *opts, H, N, ldh, nev, nex, degree, tol, evals, evecs, ldv, resid, info);
     } catch (...) {
       c.stream = own;
-      c.set_stream(own);
       throw;
     }
     c.stream = own;
-    c.set_stream(own);
     return r;
   });
 }
@@ -297,14 +294,12 @@ chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx,
     cx.ensure_work(N, ncols, cplx, false, 0);
     hipStream_t own = cx.stream;
     cx.stream = stream ? (hipStream_t)stream : own;
-    cx.set_stream(cx.stream);
     Work &w = cx.w;
     copy_cols(cplx, X, ldx, w.Xq, N, (int)N, ncols, cx.stream);
     QrOut q = qr(cx, cplx, w.Xq, w.B1, N, N, ncols, variant, 0);
     copy_cols(cplx, q.Q, N, X, ldx, (int)N, ncols, cx.stream);
     hipError_t err = hipStreamSynchronize(cx.stream);
     cx.stream = own;
-    cx.set_stream(own);
     if (err != hipSuccess) {
       set_error(std::string("qr: ") + hipGetErrorString(err));
       throw DeviceError();
@@ -331,14 +326,12 @@ chase_status chase_rayleigh_ritz(chase_dtype dtype, const void *H, int64_t N, in
     cx.ensure_work(N, ncols, cplx, false, 0);
     hipStream_t own = cx.stream;
     cx.stream = stream ? (hipStream_t)stream : own;
-    cx.set_stream(cx.stream);
     rayleigh_ritz(cx, cplx, H, ldh, N, Q, ldq, ncols, cx.w.B2, V, ldv, HV, ldhv);
     CHASE_HIP(hipMemcpyAsync(ritz, cx.w.theta, 8 * (size_t)ncols, hipMemcpyDeviceToHost,
                              cx.stream));
     CHASE_HIP(hipMemcpyAsync(cx.w.h_flag + 2, cx.w.rinfo, 4, hipMemcpyDeviceToHost, cx.stream));
     hipError_t err = hipStreamSynchronize(cx.stream);
     cx.stream = own;
-    cx.set_stream(own);
     if (err != hipSuccess) {
       set_error(std::string("rayleigh_ritz: ") + hipGetErrorString(err));
       throw DeviceError();

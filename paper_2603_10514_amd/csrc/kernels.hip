@@ -5,46 +5,9 @@
 
 #include "gemm.hpp"
 #include "kernels.hpp"
+#include "num.hpp"
 
 namespace chase {
-
-// ------------------------------------------------------- scalar helpers --
-template <typename E> struct Num;
-template <> struct Num<double> {
-  __device__ static double zero() { return 0.0; }
-  __device__ static double mul(double a, double b) { return a * b; }
-  __device__ static double cj(double a) { return a; }
-  __device__ static double abs2(double a) { return a * a; }
-  __device__ static double re(double a) { return a; }
-  __device__ static double im(double) { return 0.0; }
-  __device__ static double real(double r) { return r; }
-  __device__ static double scale(double a, double s) { return a * s; }
-  // a + (the value of lane ^ m)
-  __device__ static double add_xor(double a, int m) { return a + __shfl_xor(a, m); }
-  __device__ static double sel(bool p, double a, double b) { return p ? a : b; }
-};
-template <> struct Num<double2> {
-  __device__ static double2 zero() { return make_double2(0.0, 0.0); }
-  __device__ static double2 mul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-  }
-  __device__ static double2 cj(double2 a) { return make_double2(a.x, -a.y); }
-  __device__ static double abs2(double2 a) { return a.x * a.x + a.y * a.y; }
-  __device__ static double re(double2 a) { return a.x; }
-  __device__ static double im(double2 a) { return a.y; }
-  __device__ static double2 real(double r) { return make_double2(r, 0.0); }
-  __device__ static double2 scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-  __device__ static double2 add_xor(double2 a, int m) {
-    return make_double2(a.x + __shfl_xor(a.x, m), a.y + __shfl_xor(a.y, m));
-  }
-  // p ? a : b by components (a select of the vector struct goes through memory)
-  __device__ static double2 sel(bool p, double2 a, double2 b) {
-    return make_double2(p ? a.x : b.x, p ? a.y : b.y);
-  }
-};
-__device__ __forceinline__ double2 operator+(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 operator-(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 operator-(double2 a) { return make_double2(-a.x, -a.y); }
 
 // Deterministic block reduction of one double over 256 threads.
 __device__ __forceinline__ double block_sum256(double v, double *sh) {
@@ -481,112 +444,6 @@ __global__ __launch_bounds__(256) void k_lz_step_small(E *LV, int64_t ldv, int N
   if (t == 0) ab[(int64_t)(k + j) * nv + r] = s;
 }
 
-// --------------------------------------- small Hermitian eigensolver (Jacobi) --
-// Eigen-decomposition of a Hermitian n x n matrix, n <= kJacobiMaxN, by one
-// work-group: cyclic two-sided Jacobi in the parallel (round-robin) order,
-// each round applying n/2 disjoint rotations at once (columns of A and V,
-// then rows of A).  The 2 x 2 step for the pair (p, q) follows the symmetric
-// Schur decomposition of Golub and Van Loan (Sec. 8.5) after a phase that
-// makes a_pq real: with a_pq = |a_pq| e^{i phi}, tau = (a_qq - a_pp)/(2|a_pq|),
-// t = sign(tau)/(|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c,
-// J = [[c, s e^{i phi}], [-s e^{-i phi}, c]] and J^H A J zeroes a_pq.
-// Sweeps stop when the off-diagonal Frobenius norm falls below
-// 8 n u ||A||_F, at most kJacobiMaxSweeps; *info = 0, or 1 if that limit was
-// hit.  On exit A holds the eigenvectors as columns and theta the
-// eigenvalues, ascending (ties by index).
-template <typename E>
-__global__ __launch_bounds__(256) void k_jacobi_eig(E *A, int64_t lda, int n, double *theta,
-                                                    int *info) {
-  constexpr int MX = kJacobiMaxN;
-  __shared__ E sA[MX][MX + 1];
-  __shared__ E sV[MX][MX + 1];
-  __shared__ int sp[MX / 2], sq[MX / 2];
-  __shared__ double sc[MX / 2], ss[MX / 2];
-  __shared__ E sph[MX / 2];  // e^{i phi} of each pair
-  __shared__ double sh[256];
-  __shared__ int s_done;
-  const int t = threadIdx.x;
-  const int M = n + (n & 1);  // even order: an odd n gets an uncoupled extra index
-  for (int idx = t; idx < MX * MX; idx += 256) {
-    const int i = idx % MX, j = idx / MX;
-    E a = Num<E>::zero();
-    if (i < n && j < n) a = A[(int64_t)j * lda + i];
-    sA[i][j] = a;
-    sV[i][j] = Num<E>::real(i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  double fro = 0.0;
-  for (int idx = t; idx < M * M; idx += 256) fro += Num<E>::abs2(sA[idx % M][idx / M]);
-  fro = block_sum256(fro, sh);
-  const double stop = 8.0 * M * 0x1p-53 * sqrt(fro);
-  int sweep = 0;
-  for (; sweep < kJacobiMaxSweeps; ++sweep) {
-    double off = 0.0;
-    for (int idx = t; idx < M * M; idx += 256) {
-      const int i = idx % M, j = idx / M;
-      if (i != j) off += Num<E>::abs2(sA[i][j]);
-    }
-    off = block_sum256(off, sh);
-    if (t == 0) s_done = !(sqrt(off) > stop);
-    __syncthreads();
-    if (s_done) break;
-    for (int r = 0; r < M - 1; ++r) {
-      if (t < M / 2) {  // the round's pairs and their rotations
-        const int p = t == 0 ? r : (r + t) % (M - 1);
-        const int q = t == 0 ? M - 1 : (r - t + M - 1) % (M - 1);
-        const E apq = sA[p][q];
-        const double b = sqrt(Num<E>::abs2(apq));
-        double c = 1.0, s = 0.0;
-        E ph = Num<E>::real(1.0);
-        if (b > 0.0) {
-          const double tau = (Num<E>::re(sA[q][q]) - Num<E>::re(sA[p][p])) / (2.0 * b);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-          ph = Num<E>::scale(apq, 1.0 / b);
-        }
-        sp[t] = p; sq[t] = q; sc[t] = c; ss[t] = s; sph[t] = ph;
-      }
-      __syncthreads();
-      // columns p, q of A and V: A J, V J
-      for (int idx = t; idx < (M / 2) * M * 2; idx += 256) {
-        const int k = idx % (M / 2), rest = idx / (M / 2), i = rest % M, which = rest / M;
-        E (*X)[MX + 1] = which == 0 ? sA : sV;
-        const int p = sp[k], q = sq[k];
-        const double c = sc[k], s = ss[k];
-        const E ph = sph[k];
-        const E xp = X[i][p], xq = X[i][q];
-        X[i][p] = Num<E>::scale(xp, c) - Num<E>::scale(Num<E>::mul(Num<E>::cj(ph), xq), s);
-        X[i][q] = Num<E>::scale(Num<E>::mul(ph, xp), s) + Num<E>::scale(xq, c);
-      }
-      __syncthreads();
-      // rows p, q of A: J^H A
-      for (int idx = t; idx < (M / 2) * M; idx += 256) {
-        const int k = idx % (M / 2), j = idx / (M / 2);
-        const int p = sp[k], q = sq[k];
-        const double c = sc[k], s = ss[k];
-        const E ph = sph[k];
-        const E ap = sA[p][j], aq = sA[q][j];
-        sA[p][j] = Num<E>::scale(ap, c) - Num<E>::scale(Num<E>::mul(ph, aq), s);
-        sA[q][j] = Num<E>::scale(Num<E>::mul(Num<E>::cj(ph), ap), s) + Num<E>::scale(aq, c);
-      }
-      __syncthreads();
-    }
-  }
-  if (t == 0) info[0] = sweep == kJacobiMaxSweeps ? 1 : 0;
-  // ascending order: the rank of eigenvalue i among all (ties by index)
-  for (int i = t; i < n; i += 256) {
-    const double li = Num<E>::re(sA[i][i]);
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double lj = Num<E>::re(sA[j][j]);
-      rank += (lj < li) || (lj == li && j < i);
-    }
-    theta[rank] = li;
-    for (int row = 0; row < n; ++row) A[(int64_t)rank * lda + row] = sV[row][i];
-  }
-}
-
 // out (rows x nv, leading dimension ldo) = sum over nsplit partials (each
 // rows x nv, leading dimension ldp), keeping only the entries of row q in
 // column q % nv and zeroing the others: the coefficients of each Lanczos run
@@ -778,45 +635,39 @@ __global__ __launch_bounds__(256) void k_hh_column(E *__restrict__ P, int64_t ld
 // I - V T V^H from S = V^H V and tau: T[i][i] = tau_i and
 // T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i].  One packed upper triangle in
 // LDS holds S, and column i of T replaces column i of S once computed
-// (column i of T reads only T's earlier columns and S's column i).  Thread t
-// owns row t.
+// (column i of T reads only T's earlier columns and S's column i).  Eight
+// threads share row t's dot product (lanes 8t .. 8t+7 of the block, summed
+// by shuffles within the wave).
+constexpr int kLarftThreads = 8 * kHhMaxOuter;
 template <typename E>
-__global__ __launch_bounds__(kHhMaxOuter) void k_hh_larft(const E *S, int64_t lds, const E *tau,
-                                                          E *T, int64_t ldt, int nb) {
+__global__ __launch_bounds__(kLarftThreads) void k_hh_larft(const E *S, int64_t lds, const E *tau,
+                                                            E *T, int64_t ldt, int nb) {
   __shared__ E sh[kHhMaxOuter * (kHhMaxOuter + 1) / 2];  // (k, i), k <= i, at i (i + 1) / 2 + k
-  const int t = threadIdx.x;
-  for (int i0 = 0; i0 < nb; i0 += 8) {  // eight loads in flight per thread
-    E x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = i0 + u < nb && t <= i0 + u ? S[t + (i0 + u) * lds] : Num<E>::zero();
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (i0 + u < nb && t <= i0 + u) sh[(i0 + u) * (i0 + u + 1) / 2 + t] = x[u];
+  const int tid = threadIdx.x, t = tid >> 3, sub = tid & 7;
+  for (int idx = tid; idx < nb * nb; idx += kLarftThreads) {
+    const int r = idx % nb, c = idx / nb;
+    if (r <= c) sh[c * (c + 1) / 2 + r] = S[r + (int64_t)c * lds];
   }
   __syncthreads();
   for (int i = 0; i < nb; ++i) {
     E v = Num<E>::zero();
     if (t < i) {
       const E *si = sh + i * (i + 1) / 2;
-      E v1 = Num<E>::zero(), v2 = Num<E>::zero(), v3 = Num<E>::zero();
-      int k = t;
-      for (; k + 3 < i; k += 4) {  // four chains in flight
-        v = v + Num<E>::mul(sh[k * (k + 1) / 2 + t], si[k]);
-        v1 = v1 + Num<E>::mul(sh[(k + 1) * (k + 2) / 2 + t], si[k + 1]);
-        v2 = v2 + Num<E>::mul(sh[(k + 2) * (k + 3) / 2 + t], si[k + 2]);
-        v3 = v3 + Num<E>::mul(sh[(k + 3) * (k + 4) / 2 + t], si[k + 3]);
-      }
-      for (; k < i; ++k) v = v + Num<E>::mul(sh[k * (k + 1) / 2 + t], si[k]);
-      v = -Num<E>::mul(tau[i], (v + v1) + (v2 + v3));
-    } else if (t == i) {
-      v = tau[i];
+      for (int k = t + sub; k < i; k += 8) v = v + Num<E>::mul(sh[k * (k + 1) / 2 + t], si[k]);
     }
+    v = Num<E>::add_xor(v, 1);
+    v = Num<E>::add_xor(v, 2);
+    v = Num<E>::add_xor(v, 4);
+    if (t < i) v = -Num<E>::mul(tau[i], v);
+    else if (t == i) v = tau[i];
     __syncthreads();
-    if (t <= i) sh[i * (i + 1) / 2 + t] = v;
+    if (t <= i && sub == 0) sh[i * (i + 1) / 2 + t] = v;
     __syncthreads();
   }
-  for (int i = 0; i < nb; ++i)
-    if (t < nb) T[t + i * ldt] = t <= i ? sh[i * (i + 1) / 2 + t] : Num<E>::zero();
+  for (int idx = tid; idx < nb * nb; idx += kLarftThreads) {
+    const int r = idx % nb, c = idx / nb;
+    T[r + (int64_t)c * ldt] = r <= c ? sh[c * (c + 1) / 2 + r] : Num<E>::zero();
+  }
 }
 
 // out (rows x cols) = sum over nsplit partials (fixed order).
@@ -1046,17 +897,6 @@ void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void 
                        nv, (double *)W, ldw, ab, k);
 }
 
-void jacobi_eig(bool cplx, void *A, int64_t lda, int n, double *theta, int *info,
-                hipStream_t s) {
-  if (n < 1 || n > kJacobiMaxN || lda < n) throw InvalidArg();
-  if (cplx)
-    hipLaunchKernelGGL(k_jacobi_eig<double2>, dim3(1), dim3(256), 0, s, (double2 *)A, lda, n,
-                       theta, info);
-  else
-    hipLaunchKernelGGL(k_jacobi_eig<double>, dim3(1), dim3(256), 0, s, (double *)A, lda, n, theta,
-                       info);
-}
-
 static unsigned hh_blocks(int Mp, int jj) {
   const int rbeg = jj >= 1 ? jj - 1 : 0;
   return std::min<unsigned>(kHhMaxBlocks, blocks(Mp - rbeg, 256));
@@ -1080,10 +920,10 @@ void hh_larft(bool cplx, const void *S, int64_t lds, const void *tau, void *T, i
               int nb, hipStream_t s) {
   if (nb < 1 || nb > kHhMaxOuter) throw InvalidArg();
   if (cplx)
-    hipLaunchKernelGGL(k_hh_larft<double2>, dim3(1), dim3(kHhMaxOuter), 0, s, (const double2 *)S,
+    hipLaunchKernelGGL(k_hh_larft<double2>, dim3(1), dim3(kLarftThreads), 0, s, (const double2 *)S,
                        lds, (const double2 *)tau, (double2 *)T, ldt, nb);
   else
-    hipLaunchKernelGGL(k_hh_larft<double>, dim3(1), dim3(kHhMaxOuter), 0, s, (const double *)S,
+    hipLaunchKernelGGL(k_hh_larft<double>, dim3(1), dim3(kLarftThreads), 0, s, (const double *)S,
                        lds, (const double *)tau, (double *)T, ldt, nb);
 }
 

@@ -69,13 +69,49 @@ constexpr int kLzSmallMaxBasis = 128;
 void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void *W, int64_t ldw,
                    double *ab, int k, hipStream_t s);
 
-// Eigenvalues (ascending, theta) and eigenvectors (in place, columns of A)
-// of a Hermitian n x n matrix, n <= kJacobiMaxN, by one work-group (cyclic
-// Jacobi, parallel order); info[0] = 1 if kJacobiMaxSweeps did not converge.
-constexpr int kJacobiMaxN = 64;
-constexpr int kJacobiMaxSweeps = 40;
-void jacobi_eig(bool cplx, void *A, int64_t lda, int n, double *theta, int *info,
-                hipStream_t s);
+// Hermitian eigensolver of the Rayleigh-Ritz matrix (eig.hip).
+constexpr int kEigSmallMax = 64;  // LDS-resident reduction / back transform up to this order
+constexpr int kEigQrMax = 24;     // tridiagonal QR for the whole problem up to this order
+constexpr int kEigMaxN = 2560;    // largest order (LDS arrays of the reduction)
+constexpr int kDcLeaf = 16;       // largest leaf of the divide and conquer
+constexpr int kDcGemmSmall = 256; // merges up to this order multiply in one batched launch
+// A (n <= kEigSmallMax): eigenvalues ascending in theta, eigenvectors in
+// place; info[0] = 1 if the tridiagonal QR did not converge.
+void heev_small(bool cplx, void *A, int64_t lda, int n, double *theta, int *info, hipStream_t s);
+// Launch j of the reduction to tridiagonal form (A n x n, lda; V: reflector
+// j in column j below row j; tau; d, e: the tridiagonal; p vectors
+// alternate between pin (read) and pout (written)).
+void hetrd_step(bool cplx, void *A, int64_t lda, int n, int j, void *V, int64_t ldv, void *tau,
+                double *d, double *e, const void *pin, void *pout, hipStream_t s);
+// The last n - j0 <= kEigSmallMax columns of the reduction in one
+// work-group (pin: the p vector of launch j0 - 1; unused when j0 == 0).
+void hetrd_tail(bool cplx, const void *A, int64_t lda, int n, int j0, void *V, int64_t ldv,
+                void *tau, double *d, double *e, const void *pin, hipStream_t s);
+// X = H_0 ... H_{n-2} Z for n <= kEigSmallMax (one work-group).
+void ormtr_small(bool cplx, const void *V, int64_t ldv, const void *tau, const double *Z,
+                 int64_t ldz, int n, void *X, int64_t ldx, hipStream_t s);
+// The products Zk = Qg U of every merge at depth t in one launch (merge
+// orders up to kDcGemmSmall).
+void dc_gemm_small(const double *Qg, const double *U, double *Zk, int n, int t, hipStream_t s);
+// Divide and conquer on the tridiagonal (d, e) of order n: depth of the
+// tree, the leaves (eigenvalues to w, eigenvectors to the diagonal blocks of
+// Z, ld n, zero elsewhere), and per level t (D - 1 down to 0) the merge
+// steps before (deflation, secular roots, Loewner, the rank-one problem's
+// eigenvectors U, the gathered columns Qg) and after (sorted placement into
+// Zn) the products Zk = Qg U of every merge, which the caller runs.
+struct DcPtrs {
+  double *dl, *zl, *tsec, *zh, *dval;
+  int *org, *src_nd, *src_df, *srcbuf, *kcnt;
+};
+int dc_depth(int n);
+void dc_leaves(const double *d, const double *e, int n, int D, double *w, double *Z, int *info,
+               hipStream_t s);
+void dc_merge_pre(const double *e, int n, int t, const double *w, double *Zc, double *Qg,
+                  double *U, const DcPtrs &a, hipStream_t s);
+void dc_merge_post(int n, int t, double *w, const double *Zk, const double *Zc, double *Zn,
+                   const DcPtrs &a, hipStream_t s);
+// X (n x n, ldx) = Z (real, ld n) as real or complex elements.
+void real_to_elem(bool cplx, const double *Z, int n, void *X, int64_t ldx, hipStream_t s);
 
 // Householder QR helpers (geqrf convention, panels of kHhNB columns).
 constexpr int kHhNB = 32;         // columns of one panel of column steps

@@ -4,8 +4,6 @@
 // locking, the degree policy and the condition-number estimate.
 #include "solver.hpp"
 
-#include <rocsolver/rocsolver.h>
-
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -202,6 +200,10 @@ static Layout layout(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int 
       k ? al(16 * (size_t)k * nv) : 0,                                    // lz_ab
       al(kTailScratch),                                                   // SK
       al(kHhStateBytes),                                                  // hh
+      al(8 * (size_t)L), al(8 * (size_t)L),                              // eg_d eg_e
+      al(es * L), al(es * L),                                             // eg_p
+      al(es * (size_t)kHhMaxOuter * kHhMaxOuter),                         // eg_T
+      al(8 * (size_t)L * 5) + al(4 * (size_t)L * 5),                     // dc arrays
   };
   Layout lo{};
   size_t o = 0;
@@ -224,19 +226,8 @@ void Ctx::ensure_init() {
     CHASE_HIP(hipStreamCreate(&stream));
     own_stream = true;
   }
-  if (rocblas_create_handle(&rb) != rocblas_status_success) {
-    set_error("rocblas_create_handle failed");
-    throw DeviceError();
-  }
-  rocblas_set_stream(rb, stream);
   for (auto &e : ev) CHASE_HIP(hipEventCreate(&e));
   init = true;
-}
-
-void Ctx::set_stream(hipStream_t s) {
-  ensure_init();
-  hipStream_t target = s ? s : stream;
-  rocblas_set_stream(rb, target);
 }
 
 void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec) {
@@ -286,6 +277,20 @@ void Ctx::ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int
   w.SK = b + lo.off[i++];
   w.sk_bytes = kTailScratch;
   w.hh = b + lo.off[i++];
+  w.eg_d = (double *)(b + lo.off[i++]);
+  w.eg_e = (double *)(b + lo.off[i++]);
+  w.eg_p[0] = b + lo.off[i++];
+  w.eg_p[1] = b + lo.off[i++];
+  w.eg_T = b + lo.off[i++];
+  {
+    double *dd = (double *)(b + lo.off[i]);
+    int *ii = (int *)(b + lo.off[i] + al(8 * (size_t)L * 5));
+    w.dc.dl = dd; w.dc.zl = dd + L; w.dc.tsec = dd + 2 * (size_t)L;
+    w.dc.zh = dd + 3 * (size_t)L; w.dc.dval = dd + 4 * (size_t)L;
+    w.dc.org = ii; w.dc.src_nd = ii + L; w.dc.src_df = ii + 2 * (size_t)L;
+    w.dc.srcbuf = ii + 3 * (size_t)L; w.dc.kcnt = ii + 4 * (size_t)L;
+    ++i;
+  }
   // pinned host mirrors, grown on demand
   const int lz_cols = std::max(lz_steps, 1) * std::max(lz_nvec, 1);
   if (L > h_cap_L || lz_cols > h_cap_lz) {
@@ -320,7 +325,6 @@ void Ctx::release() {
   w = Work();
   if (init) {
     for (auto &e : ev) (void)hipEventDestroy(e);
-    rocblas_destroy_handle(rb);
     if (own_stream) (void)hipStreamDestroy(stream);
   }
   init = false;
@@ -417,7 +421,8 @@ int filter(Ctx &c, bool cplx, bool f32, const void *H, int64_t ldh, int64_t N, v
 
 // G = X^H X (upper triangle by tiles, deterministic split-K) -> Hermitian G.
 static void gram(Ctx &c, bool cplx, const void *X, int64_t ldx, int64_t N, int L, void *G,
-                 int average_with_B, const void *B = nullptr, int64_t ldB = 0) {
+                 int average_with_B, const void *B = nullptr, int64_t ldB = 0,
+                 bool qr_flag = true) {
   Work &w = c.w;
   // partials buffer holds w.nsplit * w.L^2 elements: never use more splits
   const int64_t cap = (int64_t)w.nsplit * w.L * w.L / ((int64_t)L * L);
@@ -430,7 +435,7 @@ static void gram(Ctx &c, bool cplx, const void *X, int64_t ldx, int64_t N, int L
   a.tri = average_with_B ? 0 : 1;
   a.k_per_split = (int)(((N + ns - 1) / ns + bk - 1) / bk * bk);
   a.C = w.P; a.ldc = L; a.split_stride = (int64_t)L * L;
-  a.flag = average_with_B ? nullptr : w.flag;
+  a.flag = (average_with_B || !qr_flag) ? nullptr : w.flag;
   gemm(cplx, false, true, false, false, CHASE_GRAM_SHAPE, a, ns, c.stream);
   reduce_hermitian(cplx, w.P, ns, (int64_t)L * L, L, L, G, L, average_with_B, c.stream);
 }
@@ -504,13 +509,6 @@ static void trsm(Ctx &c, bool cplx, const void *Xin, void *Xout, int64_t ld, int
   a.C = Xout; a.ldc = ld;
   a.flag = c.w.flag;
   gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);
-}
-
-static void rocsolver_check(rocblas_status st, const char *what) {
-  if (st != rocblas_status_success) {
-    set_error(std::string(what) + " failed with rocblas status " + std::to_string((int)st));
-    throw DeviceError();
-  }
 }
 
 // Split count of a K-split product with `tiles` output tiles over K rows.
@@ -686,6 +684,87 @@ QrOut qr(Ctx &c, bool cplx, void *X, void *Xalt, int64_t ld, int64_t N, int L, c
   return qr_finish(c, cplx, p, ld, N, L);
 }
 
+// Eigenvalues (ascending, into w.theta) and eigenvectors of the Hermitian
+// n x n matrix A (ld n, destroyed) on the device; returns the eigenvector
+// matrix (n x n, ld n): A itself for n <= kEigQrMax, else w.R.  w.rinfo is
+// set to 1 if a tridiagonal QR (small orders, leaves) did not converge.
+// Above kEigQrMax: Householder reduction T = Q^H A Q (one launch per column
+// down to kEigSmallMax remaining columns, the rest in one work-group),
+// divide and conquer on T (the leaves by tridiagonal QR, each level's
+// rank-one merges batched, their products Z = Q_hat U batched for small
+// merges and on the MFMA GEMM core for large ones), then X = Q Z (one
+// work-group up to kEigSmallMax, else block reflectors of kHhMaxOuter
+// columns, last first).
+// Buffers: V = w.G; the divide and conquer's Z ping-pong in w.Ri / w.T, the
+// gathered columns in w.P, U in w.R, the products in w.A; X in w.R.
+static const void *heevd(Ctx &c, bool cplx, void *A, int n) {
+  Work &w = c.w;
+  hipStream_t st = c.stream;
+  const size_t es = cplx ? 16 : 8;
+  fill_zero(false, w.rinfo, 1, 1, 1, st);
+  if (n <= kEigQrMax) {
+    heev_small(cplx, A, n, n, w.theta, w.rinfo, st);
+    return A;
+  }
+  if (n > kEigMaxN) {
+    set_error("Rayleigh-Ritz: " + std::to_string(n) + " columns exceed the eigensolver's " +
+              std::to_string(kEigMaxN));
+    throw InvalidArg();
+  }
+  // 1. reduction to tridiagonal form: one launch per column while more than
+  // kEigSmallMax columns remain, the rest in one work-group
+  fill_zero(cplx, w.G, n, n, n, st);
+  const int j0 = std::max(0, n - kEigSmallMax);
+  for (int j = 0; j < j0; ++j)
+    hetrd_step(cplx, A, n, n, j, w.G, n, w.tau, w.eg_d, w.eg_e, w.eg_p[(j + 1) & 1],
+               w.eg_p[j & 1], st);
+  hetrd_tail(cplx, A, n, n, j0, w.G, n, w.tau, w.eg_d, w.eg_e, w.eg_p[(j0 + 1) & 1], st);
+  // 2. divide and conquer
+  const int D = dc_depth(n);
+  double *Zc = (double *)w.Ri, *Zn = (double *)w.T;
+  double *Qg = (double *)w.P, *U = (double *)w.R, *Zk = (double *)A;
+  fill_zero(false, Zc, n, n, n, st);
+  fill_zero(false, Zn, n, n, n, st);
+  dc_leaves(w.eg_d, w.eg_e, n, D, w.theta, Zc, w.rinfo, st);
+  for (int t = D - 1; t >= 0; --t) {
+    dc_merge_pre(w.eg_e, n, t, w.theta, Zc, Qg, U, w.dc, st);
+    if (((n + (1 << t) - 1) >> t) <= kDcGemmSmall) {
+      dc_gemm_small(Qg, U, Zk, n, t, st);
+    } else for (int i = 0; i < (1 << t); ++i) {
+      const int s0 = (int)(((int64_t)i * n) >> t);
+      const int nn = (int)(((int64_t)(i + 1) * n) >> t) - s0;
+      GemmArgs a = gargs();
+      a.A = Qg + s0 + (size_t)s0 * n; a.lda = n;
+      a.B = U + (size_t)s0 * n; a.ldb = n;
+      a.M = nn; a.N = nn; a.K = nn;
+      a.C = Zk + s0 + (size_t)s0 * n; a.ldc = n;
+      gemm(false, false, false, false, false, nn >= 256 ? GEMM_BIG : GEMM_SMALL, a, 1, st);
+    }
+    dc_merge_post(n, t, w.theta, Zk, Zc, Zn, w.dc, st);
+    std::swap(Zc, Zn);
+  }
+  // 3. X = H_0 ... H_{n-2} Z
+  void *X = w.R;
+  if (n <= kEigSmallMax) {
+    ormtr_small(cplx, w.G, n, w.tau, Zc, n, n, X, n, st);
+    CHASE_HIP(hipGetLastError());
+    return X;
+  }
+  real_to_elem(cplx, Zc, n, X, n, st);
+  const int nb = kHhMaxOuter;
+  for (int j0 = (n - 2) / nb * nb; j0 >= 0; j0 -= nb) {
+    const int nbp = std::min(nb, n - 1 - j0);
+    const int64_t Mp = n - 1 - j0;
+    const void *Vp = (const char *)w.G + es * ((size_t)(j0 + 1) + (size_t)j0 * n);
+    gram(c, cplx, Vp, n, Mp, nbp, w.T, 0, nullptr, 0, false);  // V^H V
+    hh_larft(cplx, w.T, nbp, (const char *)w.tau + es * j0, w.eg_T, nbp, nbp, st);
+    apply_block_reflector(c, cplx, Vp, n, Mp, nbp, w.eg_T, false, (char *)X + es * (j0 + 1), n,
+                          n);
+  }
+  CHASE_HIP(hipGetLastError());
+  return X;
+}
+
 // Rayleigh-Ritz on the orthonormal Q (N x Lp): W = H Q, A~ = Q^H W
 // symmetrised, (theta, Z) = eigh(A~), V = Q Z, HV = W Z.
 void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const void *Q,
@@ -700,23 +779,11 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
     gemm(cplx, false, true, false, false, GEMM_BIG, a, 1, c.stream);
   }
   gram(c, cplx, Q, ldq, N, Lp, w.A, 1, W, N);
-  if (Lp <= kJacobiMaxN) {
-    // one work-group; the vendor divide-and-conquer costs dozens of launches
-    jacobi_eig(cplx, w.A, Lp, Lp, w.theta, w.rinfo, c.stream);
-  } else {
-    rocblas_status st;
-    if (cplx)
-      st = rocsolver_zheevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp,
-                            (rocblas_double_complex *)w.A, Lp, w.theta, w.E, w.rinfo);
-    else
-      st = rocsolver_dsyevd(c.rb, rocblas_evect_original, rocblas_fill_upper, Lp, (double *)w.A,
-                            Lp, w.theta, w.E, w.rinfo);
-    rocsolver_check(st, cplx ? "rocsolver_zheevd" : "rocsolver_dsyevd");
-  }
+  const void *Z = heevd(c, cplx, w.A, Lp);
   {
     GemmArgs a = bigargs(c);
     a.A = Q; a.lda = ldq;
-    a.B = w.A; a.ldb = Lp;
+    a.B = Z; a.ldb = Lp;
     a.M = (int)N; a.N = Lp; a.K = Lp;
     a.C = Vout; a.ldc = ldv;
     gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);
@@ -724,7 +791,7 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
   {
     GemmArgs a = bigargs(c);
     a.A = W; a.lda = N;
-    a.B = w.A; a.ldb = Lp;
+    a.B = Z; a.ldb = Lp;
     a.M = (int)N; a.N = Lp; a.K = Lp;
     a.C = HV; a.ldc = ldhv;
     gemm(cplx, false, false, false, false, GEMM_BIG, a, 1, c.stream);

@@ -1,11 +1,10 @@
 // Internal interface of the host driver (not part of the C ABI).
 #pragma once
-#include <rocblas/rocblas.h>
-
 #include <vector>
 
 #include "../../include/chase.h"
 #include "common.hpp"
+#include "kernels.hpp"
 
 namespace chase {
 
@@ -28,6 +27,13 @@ struct Work {
   double *lz_ab = nullptr;
   void *SK = nullptr;                                   // remainder-split partials
   void *hh = nullptr;                                   // Householder QR state
+  // eigensolver of the Rayleigh-Ritz matrix: tridiagonal (d, e), the two
+  // p vectors of the reduction, the divide and conquer arrays, the T of one
+  // block reflector of the back-transform
+  double *eg_d = nullptr, *eg_e = nullptr;
+  void *eg_p[2] = {nullptr, nullptr};
+  void *eg_T = nullptr;
+  DcPtrs dc = {};
   size_t sk_bytes = 0;
   // pinned host mirrors
   double *h_theta = nullptr, *h_resid = nullptr, *h_ab = nullptr;
@@ -42,7 +48,6 @@ size_t work_bytes(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_
 struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  rocblas_handle rb = nullptr;
   Work w;
   hipEvent_t ev[8] = {};
   bool init = false;
@@ -50,7 +55,6 @@ struct Ctx {
   void ensure_init();
   void free_pinned();
   void ensure_work(int64_t N, int L, bool cplx, bool mixed, int lz_steps, int lz_nvec = 1);
-  void set_stream(hipStream_t s);
   void release();
 };
 

@@ -245,11 +245,81 @@ def test_rayleigh_ritz_clustered_small(P, gpu, L, cplx, kind):
     assert np.max(np.linalg.norm(R, axis=0)) <= 1e-12 * scale
 
 
+EIG_CASES = [
+    # L (order of the projected problem), cplx, spectrum of H
+    (25, True, "uniform"), (48, False, "cluster"), (65, True, "uniform"), (65, False, "uniform"),
+    (129, False, "uniform"), (300, False, "uniform"),
+    (300, True, "repeated"), (700, True, "cluster"), (1300, True, "dft"),
+    (1300, False, "cluster"), (1900, True, "dft"),
+]
+
+
+@pytest.mark.parametrize("L,cplx,kind", EIG_CASES)
+def test_rayleigh_ritz_eigensolver_large(P, gpu, L, cplx, kind):
+    """The library's own eigensolver of the projected matrix above 64 columns
+    (Householder reduction to tridiagonal form, divide and conquer, back
+    transform) against the oracle's Rayleigh-Ritz (LAPACK eigh): Ritz values
+    to 1e-12 ||A||, the projected eigen-residual Q^H (HV - V Theta) and the
+    orthogonality of V to a few hundred u, and the invariant subspaces of
+    well-separated groups to within the perturbation bound.  The DFT-like
+    spectra put most Ritz values in a dense cluster (deflation); the
+    repeated one has eigenvalues of multiplicity 5 and 9."""
+    print("eigensolver case", L, cplx, kind, flush=True)
+    N = L + 100
+    rng = np.random.default_rng(61)
+    exact = None
+    if kind == "cluster":
+        # Q spans an exact invariant subspace whose eigenvalues hold a cluster
+        # of L / 2 values 1e-9 apart (the deflation of the merges)
+        Qf, _ = np.linalg.qr(synth.start_block(N, N, 63, cplx))
+        exact = np.sort(np.concatenate([-1.5 + 1e-9 * np.arange(L // 2),
+                                        rng.uniform(-1.0, 0.0, L - L // 2)]))
+        lam = np.concatenate([exact, rng.uniform(1.0, 50.0, N - L)])
+        H = (Qf * lam) @ Qf.conj().T
+        H = np.asfortranarray(0.5 * (H + H.conj().T))
+        W, _ = np.linalg.qr(synth.start_block(L, L, 65, cplx))
+        Q = np.asfortranarray(Qf[:, :L] @ W)
+    elif kind == "repeated":
+        H, lam = synth.planted_numpy(N, "uniform", 62, cplx)
+        Qf, _ = np.linalg.qr(synth.start_block(N, N, 63, cplx))
+        lam = np.sort(lam)
+        lam[3:8] = lam[3]
+        lam[100:109] = lam[100]
+        H = np.asfortranarray(0.5 * ((Qf * lam) @ Qf.conj().T + ((Qf * lam) @ Qf.conj().T).conj().T))
+    else:
+        H, lam = synth.planted_numpy(N, kind, 62, cplx)
+    if exact is None:
+        Q, _ = np.linalg.qr(synth.start_block(N, L, 64, cplx))
+        Q = np.asfortranarray(Q)
+    th_ref, V_ref, HV_ref = orr.rayleigh_ritz(H, Q)
+    th, V, HV = P.chase_rayleigh_ritz(to_dev(H, gpu), to_dev(Q, gpu))
+    Vh, HVh = to_host(V), to_host(HV)
+    scale = float(np.max(np.abs(lam)))
+    err = float(np.max(np.abs(th - th_ref)))
+    resid = float(np.max(np.linalg.norm(Q.conj().T @ (HVh - Vh * th[None, :]), axis=0)))
+    orth = float(np.linalg.norm(Vh.conj().T @ Vh - np.eye(L)))
+    print("  eig err %.2e resid %.2e orth %.2e (||A|| %.1f)" % (err, resid, orth, scale), flush=True)
+    assert err <= 1e-12 * scale
+    if exact is not None:
+        assert np.max(np.abs(th - exact)) <= 1e-12 * scale
+    assert resid <= 300 * L * U64 * scale / 10
+    assert orth <= 300 * L * U64
+    # invariant subspaces of groups separated by more than 1e-6 ||A||
+    groups = np.split(np.arange(L), np.where(np.diff(th_ref) > 1e-6 * scale)[0] + 1)
+    worst = 0.0
+    for g in groups[:: max(1, len(groups) // 40)]:
+        others = np.delete(th_ref, g)
+        gap = float(np.min(np.abs(others[:, None] - th_ref[g][None, :]))) if others.size else scale
+        worst = max(worst, _subspace_gap(Vh[:, g], V_ref[:, g]) / (1e3 * U64 * scale / gap))
+    print("  worst subspace ratio to bound %.3f" % worst, flush=True)
+    assert worst <= 1.0
+
+
 @pytest.mark.parametrize("N,L,cplx", [(1000, 60, False), (600, 37, True), (200, 130, False),
                                       (500, 64, True), (300, 1, False), (400, 65, True)])
 def test_rayleigh_ritz_and_residuals(P, gpu, N, L, cplx):
-    """Up to 64 columns the projected eigenproblem is solved by the library's
-    one-work-group Jacobi kernel, above by the vendor divide-and-conquer."""
+    """Up to 64 columns the projected eigenproblem is solved in one
+    work-group (the matrix in LDS), above by the multi-launch solver."""
     H, lam = synth.planted_numpy(N, "uniform", 13, cplx)
     Q, _ = np.linalg.qr(synth.start_block(N, L, 14, cplx))
     Q = np.asfortranarray(Q)
