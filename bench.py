@@ -72,12 +72,18 @@ def kernel_source_sha():
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
+PMC_SUMMARY = {"c2": "filter_gemm_c2_complex_n20000_pmc.md",
+               "c3": "filter_gemm_c3_mixed_n30000_pmc.md",
+               "c4": "filter_gemm_c4_real_n10000_pmc.md"}
+
+
 def measured_traffic(workload):
-    """Calibrated FETCH_SIZE + WRITE_SIZE bytes per filter dispatch from the
-    committed rocprofv3 summary, or None when the kernel changed since."""
-    if workload != "c2":
+    """Calibrated FETCH_SIZE + WRITE_SIZE bytes per dispatch of the dominant
+    filter kernel from the committed rocprofv3 summary, or None when there is
+    none or the kernel changed since."""
+    if workload not in PMC_SUMMARY:
         return None
-    f = os.path.join(ROOT, "profiles", "filter_gemm_c2_complex_n20000_pmc.md")
+    f = os.path.join(ROOT, "profiles", PMC_SUMMARY[workload])
     if not os.path.exists(f):
         return None
     vals = {}
@@ -215,6 +221,9 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-mixed-pair", action="store_true",
+                    help="default workload: skip the untimed mixed-vs-FP64 solve pair of the "
+                         "N = 30000 workload that runs after the timed steps")
     ap.add_argument("--cache-dir", default=None,
                     help="save the generated matrix here, or load it if already saved")
     ap.add_argument("--generate-only", action="store_true")
@@ -299,7 +308,6 @@ def main():
     launches = sum(r["info"]["filter_launches"] for r in results)
     fp32_iters = sum(r["info"]["filter_fp32_iters"] for r in results)
     iters = sum(r["info"]["iters"] for r in results)
-    n_steps = sum(x["deg_max"] for r in results for x in r["log"])  # degree steps
     # per-precision filter rates; the roofline entry is the kernel with the
     # larger share of filter time (FP32 and FP64 flops are never mixed)
     mv32 = sum(r["info"]["matvecs_fp32"] for r in results)
@@ -318,15 +326,26 @@ def main():
     # per-step roofline: step i with l'_i active columns cannot take less
     # than max(fx N^2 l'_i / peak, s (N^2 + 3 N l'_i) / HBM), executed flops
     es = (16.0 if wl["cplx"] else 8.0) / (2.0 if prec == "f32" else 1.0)
+    # the FP64 part of an iteration is its first ncols - ncols_fp32 columns,
+    # the FP32 part the rest; algorithmic bytes of a step: s (N^2 + 3 N l')
     t_star = 0.0
+    alg_bytes = {"f64": 0.0, "f32": 0.0}
     for r in results:
         for x in r["log"]:
-            d = np.asarray(x["degrees"])
-            pk = PEAK["f32" if x["filter_prec"] == 1 else "f64"] * 1e12
-            bpe = (16.0 if wl["cplx"] else 8.0) / (2.0 if x["filter_prec"] == 1 else 1.0)
-            for i in range(1, int(d.max()) + 1 if d.size else 1):
-                lp = float(np.sum(d >= i))
-                t_star += max(fx * float(N) ** 2 * lp / pk, bpe * (float(N) ** 2 + 3.0 * N * lp) / 8e12)
+            d_all = np.asarray(x["degrees"])
+            n32 = int(x["ncols_fp32"])
+            for part, d in (("f64", d_all[:d_all.size - n32]), ("f32", d_all[d_all.size - n32:])):
+                if d.size == 0:
+                    continue
+                pk = PEAK[part] * 1e12
+                bpe = (16.0 if wl["cplx"] else 8.0) / (2.0 if part == "f32" else 1.0)
+                for i in range(1, int(d.max()) + 1):
+                    lp = float(np.sum(d >= i))
+                    b = bpe * (float(N) ** 2 + 3.0 * N * lp)
+                    alg_bytes[part] += b
+                    t_star += max(fx * float(N) ** 2 * lp / pk, b / 8e12)
+    launches32 = sum(r["info"]["filter_launches_fp32"] for r in results)
+    klaunches = launches32 if prec == "f32" else launches - launches32
     scale = float(np.max(np.abs(lam)))
     eig_err = max(float(np.max(np.abs(r["evals"] - lam[:nev]))) / scale for r in results)
     # per eigenvalue: max_i |lambda_i - planted_i| / |planted_i|
@@ -377,13 +396,12 @@ def main():
                      "paper_convention": "%d N^2 flops per MatVec" % int(f),
                      "traffic": measured_traffic(args.workload),
                      "traffic_unit": "bytes per filter dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     # es (N^2 + 3 N l') per degree step (H once; X, X_prev and the
-                     # output once), summed over the steps, per dispatch
-                     "algorithmic_bytes_per_dispatch": (16.0 if wl["cplx"] else 8.0) * (
-                         float(N) ** 2 * n_steps + 3.0 * N * matvecs) / max(launches, 1),
+                     # s (N^2 + 3 N l') per degree step (H once; X, X_prev and the
+                     # output once), summed over this kernel's steps, per dispatch
+                     "algorithmic_bytes_per_dispatch": alg_bytes[prec] / max(klaunches, 1),
                      "kernel": "filter GEMM (gemm_kernel, EPI_FILTER, %s)" % prec,
-                     "launches": launches, "avg_launch_ms": t_filter / max(launches, 1) * 1e3,
-                     "executed_flops_per_launch": fx * float(N) ** 2 * matvecs / max(launches, 1)},
+                     "launches": klaunches, "avg_launch_ms": ktime / max(klaunches, 1) * 1e3,
+                     "executed_flops_per_launch": kflops / max(klaunches, 1)},
     }
     if wl["precision"] == 1:
         r32 = f * float(N) ** 2 * mv32 / max(t32, 1e-12) / 1e12
@@ -416,7 +434,45 @@ def main():
                             "deg_max": x["deg_max"]} for x in rd["log"]]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(H, wl, args.cpu_cols, args.cpu_degree)
+    if args.workload == "c2" and not args.no_mixed_pair:
+        del H, evecs
+        torch.cuda.empty_cache()
+        out["mixed_vs_fp64_n30000"] = mixed_pair()
     print(json.dumps(out), flush=True)
+
+
+def mixed_pair():
+    """Untimed: one solve of the N = 30000 workload with the FP32 filter and
+    one in plain FP64 on the same matrix and start block (a child process,
+    after the timed steps), reported beside the default workload's line."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--workload", "c3", "--steps", "1",
+           "--warmup", "0", "--no-cpu-baseline"]
+    log("mixed-vs-FP64 pair (N = 30000): " + " ".join(cmd[2:]))
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                           timeout=480)
+    except subprocess.TimeoutExpired:
+        return {"error": "timed out"}
+    sys.stderr.write(r.stderr[-2000:])
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": "exit status %d" % r.returncode}
+    d = json.loads(lines[-1])
+    m = d.get("mixed", {})
+    return {"workload": d["config"]["workload"], "tol": d["config"]["tol"],
+            "mixed_time_to_solution_s": d["time_to_solution_s"],
+            "fp64_time_to_solution_s": m.get("fp64_time_to_solution_s"),
+            "mixed_vs_fp64_speedup": m.get("mixed_vs_fp64_speedup"),
+            "mixed_max_eig_err_rel": d["max_eig_err_rel"],
+            "mixed_max_eig_err_rel_per_eigenvalue": d["max_eig_err_rel_per_eigenvalue"],
+            "fp64_max_eig_err_rel": m.get("fp64_max_eig_err_rel"),
+            "max_abs_eig_diff_mixed_vs_fp64_rel": m.get("max_abs_eig_diff_mixed_vs_fp64_rel"),
+            "mixed_max_resid": d["max_resid"], "mixed_converged": d["converged"],
+            "fp32_filter_frac_of_fp32_peak": m.get("fp32_frac_of_peak"),
+            "fp64_filter_frac_of_fp64_peak": m.get("fp64_frac_of_peak"),
+            "fp32_matvec_share": m.get("fp32_matvec_share"),
+            "iters": d["iters_per_solve"], "matvecs": d["matvecs_per_solve"]}
 
 
 if __name__ == "__main__":

@@ -86,7 +86,10 @@ typedef struct chase_iter_log {
   double qr_shift;       /* the shift s = 11 (N l + l (l + 1)) u ||X||_F^2 added
                             to the Gram matrix (u = 2^-53); NaN otherwise        */
   int32_t ncols;         /* active (filtered) columns of this iteration        */
-  const int32_t *degrees; /* their degrees, ascending (valid during log_cb)    */
+  const int32_t *degrees; /* their degrees (valid during log_cb): ascending over
+                             the first ncols - ncols_fp32 (FP64 filter) and over
+                             the last ncols_fp32 (FP32 filter)                  */
+  int32_t ncols_fp32;    /* columns of this iteration filtered in FP32          */
 } chase_iter_log;
 
 typedef struct chase_opts {
@@ -146,6 +149,7 @@ typedef struct chase_info {
   double t_filter_fp32;      /* part of t_filter spent in FP32 filter steps     */
   double ritz_max;           /* largest Ritz value of the last Rayleigh-Ritz
                                 (the lambda_l estimate for a warm restart)      */
+  int32_t filter_launches_fp32; /* part of filter_launches in FP32             */
 } chase_info;
 
 /* Defaults: dtype REAL64, FP64, deg_opt 1, degrees [1, 36], margin 2,

@@ -41,7 +41,7 @@ class ChaseIterLog(ctypes.Structure):
                 ("t_qr", ctypes.c_double), ("t_rr", ctypes.c_double),
                 ("t_resid", ctypes.c_double), ("qr_fro2", ctypes.c_double),
                 ("qr_shift", ctypes.c_double), ("ncols", ctypes.c_int32),
-                ("degrees", ctypes.POINTER(ctypes.c_int32))]
+                ("degrees", ctypes.POINTER(ctypes.c_int32)), ("ncols_fp32", ctypes.c_int32)]
 
 
 LOG_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(ChaseIterLog), ctypes.c_void_p)
@@ -76,7 +76,7 @@ class ChaseInfo(ctypes.Structure):
                 ("t_lanczos", ctypes.c_double), ("lambda_1", ctypes.c_double),
                 ("lambda_l", ctypes.c_double), ("lambda_max", ctypes.c_double),
                 ("matvecs_fp32", ctypes.c_int64), ("t_filter_fp32", ctypes.c_double),
-                ("ritz_max", ctypes.c_double)]
+                ("ritz_max", ctypes.c_double), ("filter_launches_fp32", ctypes.c_int32)]
 
 
 _p = ctypes.c_void_p

@@ -964,15 +964,19 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
                     e, gamma, (char *)w.Xq + es * (size_t)k * N, N);
     CHASE_HIP(hipEventRecord(c.ev[5], s));
     int64_t mv32 = 0;
+    int nl32 = f32 ? nl : 0;
     if (nW < Lp) {  // the buffer columns through the FP32 filter
       const std::vector<int> msB(msorted.begin() + nW, msorted.end());
       gather_cols(cplx, true, evecs, ldv, w.X0, N, (int)N, Lp - nW, w.perm + nW, s);
-      nl += filter(c, cplx, true, w.H32, N, N, bufs, N, Lp - nW, msB, cc, e, gamma,
-                   (char *)w.Xq + es * (size_t)(k + nW) * N, N);
+      const int nb = filter(c, cplx, true, w.H32, N, N, bufs, N, Lp - nW, msB, cc, e, gamma,
+                            (char *)w.Xq + es * (size_t)(k + nW) * N, N);
+      nl += nb;
+      nl32 += nb;
       for (int v : msB) mv32 += v;
     }
     CHASE_HIP(hipEventRecord(c.ev[1], s));
     inf.filter_launches += nl;
+    inf.filter_launches_fp32 += nl32;
     if (f32) inf.filter_fp32_iters++;
     int64_t mv = 0;
     int mmax = 0, mmin = 1 << 30;
@@ -1055,6 +1059,7 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     rec.cond_exact = kappa;
     rec.ncols = Lp;
     rec.degrees = msorted.data();
+    rec.ncols_fp32 = f32 ? Lp : Lp - nW;
     rec.c = cc; rec.e = e; rec.gamma = gamma; rec.lam1 = lam1;
     if (o.log_cb) o.log_cb(&rec, o.log_user);
     k = j;
