@@ -116,9 +116,10 @@ class Server:
         self.log = []
 
     # ------------------------------------------------------------------ API
-    def run(self, requests, clock=None):
+    def run(self, requests, clock=None, progress=None):
         """Serve requests (sorted by arrival) until all have finished.
-        Returns the list of requests with their results filled in."""
+        Returns the list of requests with their results filled in;
+        progress(msg), if given, is called as each request finishes."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
             if r.N > self.N_max or r.nev > self.nev_max or r.nex > self.nex_max:
@@ -144,10 +145,16 @@ class Server:
                 st = s.handle.query()
                 if st == P.CHASE_EBUSY:
                     continue
+                r = s.req
                 self._finish_step(s, st, time.perf_counter() - t0)
                 progressed = True
                 if s.req is None:
                     done += 1
+                    if progress:
+                        progress("request %d done (N=%d): latency %.2f s, %d/%d finished"
+                                 % (r.rid, r.N, r.t_done - r.arrival, done, len(reqs)))
+                elif progress:
+                    progress("request %d (N=%d) step %d done" % (r.rid, r.N, s.step))
             # admission: the oldest request that fits, with bounded bypass
             for s in self.slots:
                 if s.req is not None or not waiting:
