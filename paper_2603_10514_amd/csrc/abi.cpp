@@ -295,6 +295,8 @@ chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx,
     hipStream_t own = cx.stream;
     cx.stream = stream ? (hipStream_t)stream : own;
     Work &w = cx.w;
+    w.h_flag[3] = 0;
+    hh_panel_clear_error(w.hh, cx.stream);
     copy_cols(cplx, X, ldx, w.Xq, N, (int)N, ncols, cx.stream);
     QrOut q = qr(cx, cplx, w.Xq, w.B1, N, N, ncols, variant, 0);
     copy_cols(cplx, q.Q, N, X, ldx, (int)N, ncols, cx.stream);
@@ -302,6 +304,10 @@ chase_status chase_qr_factor(chase_dtype dtype, void *X, int64_t N, int64_t ldx,
     cx.stream = own;
     if (err != hipSuccess) {
       set_error(std::string("qr: ") + hipGetErrorString(err));
+      throw DeviceError();
+    }
+    if (w.h_flag[3] != 0) {
+      set_error("qr: a Householder panel launch's grid barrier timed out");
       throw DeviceError();
     }
     if (chol_failed) *chol_failed = q.failed ? 1 : 0;

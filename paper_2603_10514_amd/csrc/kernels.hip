@@ -631,6 +631,211 @@ __global__ __launch_bounds__(256) void k_hh_column(E *__restrict__ P, int64_t ld
   if (t < D) partc[(int64_t)blockIdx.x * D + t] = s_red[0][t] + s_red[1][t] + s_red[2][t] + s_red[3][t];
 }
 
+// The same panel factorisation in one cooperative launch: block b holds
+// rows [b R, (b + 1) R) of the panel (all nbp columns) in LDS from start to
+// end, so a column step reads and writes only LDS; the steps are separated
+// by a grid barrier instead of kernel boundaries.  Column step j:
+//  * every block applies reflector j - 1 to its rows (v_r = P[r, j-1] sc for
+//    r > j - 1, v = 1 at the pivot row; P[r, c] -= conj(tau) v_r w_c for
+//    c > j - 1) and, in the same pass, sums s_c = sum_{r > j} conj(P[r, j])
+//    P[r, c] (c >= j) over its rows into its slot of the partial sums; the
+//    block holding row j publishes that row;
+//  * grid barrier;
+//  * every block adds the partial sums of all blocks in block order (all
+//    agree bit for bit) and forms beta, tau, the scale 1 / (alpha - beta)
+//    and w_c = v^H P[:, c] exactly as k_hh_column does.
+// After the last reflector the rows go back to P (R on and above the
+// diagonal, the vectors below) and to Vb (explicit vectors, unit diagonal).
+// The barrier is a counter of arrivals that starts the launch at `base`;
+// a wait longer than `limit` wall-clock ticks sets *err and stops waiting
+// (the cooperative launch makes every block resident, so a correct run
+// never gets near it).
+constexpr size_t kHpBase = kHhStateBytes - kHpStateBytes;  // panel-kernel state
+constexpr size_t kHpRow = 0, kHpCtr = 2 * 16 * kHhNB, kHpPart = kHpCtr + 256;
+static_assert(kHpPart + 2 * (size_t)kHpMaxBlocks * kHhNB * 16 <= kHpStateBytes, "hp state");
+static_assert(kHpBase >= kHhPart + 2 * kHhPartBytes, "panel state overlaps the column state");
+
+// Cross-block data (partial sums, pivot row) moves by agent-coherent loads
+// and stores (relaxed atomics at agent scope: no cache of one XCD keeps a
+// stale copy), so the barrier needs no cache write-back or invalidation:
+// the writers wait for their stores to complete, then thread 0 counts the
+// block in and waits for the others.
+__device__ __forceinline__ void hp_put(void *dst, double2 v) {
+  __hip_atomic_store((double *)dst, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((double *)dst + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void hp_put(void *dst, double v) {
+  __hip_atomic_store((double *)dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename E> __device__ __forceinline__ E hp_get(const void *src);
+template <> __device__ __forceinline__ double2 hp_get(const void *src) {
+  double2 v;
+  v.x = __hip_atomic_load((const double *)src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v.y = __hip_atomic_load((const double *)src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
+template <> __device__ __forceinline__ double hp_get(const void *src) {
+  return __hip_atomic_load((const double *)src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void hp_barrier(unsigned *ctr, unsigned target, int *err,
+                                           long long limit) {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    unsigned polls = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if ((++polls & 63) == 0) {  // now and then: another block's time-out, or ours
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if (wall_clock64() - t0 > limit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  asm volatile("" ::: "memory");
+}
+
+constexpr int kHpGroups = 32;                 // row groups: 32 x 32 = 1024 threads
+constexpr int kHpThreads = kHpGroups * kHhNB;
+constexpr int kHpLoads = 256 / kHpGroups;    // partial-sum loads in flight per thread
+constexpr int kHpUnroll = 2;                 // rows per LDS round trip of a column step
+
+template <typename E, int NB, int NG>
+__global__ __launch_bounds__(NB * NG) void k_hh_panel(E *__restrict__ P, int64_t ld, int Mp, int nbp,
+                                                  int R, E *__restrict__ Vb, int64_t ldv,
+                                                  E *__restrict__ tau, char *hs, unsigned base,
+                                                  long long limit) {
+  static_assert(NB == 32 && NG * kHpLoads >= 256, "thread (g, c): NG row groups x 32 columns");
+  constexpr int NT = NB * NG;
+  extern __shared__ __align__(16) char hp_lds[];
+  E *Pl = (E *)hp_lds;  // R x NB, row-major
+  __shared__ E s_red[NG][NB];
+  __shared__ E s_w[NB], s_row[NB];
+  __shared__ E s_ct, s_sc;
+  unsigned *ctr = (unsigned *)(hs + kHpCtr);
+  int *err = (int *)(hs + kHpCtr + 64);
+  const int t = threadIdx.x, c = t % NB, g = t / NB;
+  const int G = gridDim.x;
+  const int r0 = blockIdx.x * R;
+  const int nr = max(0, min(R, Mp - r0));  // rows of this block
+  for (int idx = t; idx < nr * nbp; idx += NT) {
+    const int rl = idx % nr, cc = idx / nr;
+    Pl[rl * NB + cc] = P[(int64_t)r0 + rl + (int64_t)cc * ld];
+  }
+  __syncthreads();
+  for (int j = 0; j <= nbp; ++j) {
+    const int p = j - 1;
+    const bool upd = j >= 1, fact = j < nbp;
+    const E ct = upd ? s_ct : Num<E>::zero(), sc = upd ? s_sc : Num<E>::zero();
+    const E wc = (upd && c > p && c < nbp) ? s_w[c] : Num<E>::zero();
+    const E wj = (upd && fact) ? s_w[j] : Num<E>::zero();
+    E acc = Num<E>::zero();
+    const int jc = fact ? j : nbp - 1;  // a valid column to read when there is no next one
+    // rows g, g + NG, ... of the block, kHpUnroll at a time: all their old
+    // values are read first (the compiler barrier keeps these reads ahead of
+    // the writes of other lanes of this wave to the same rows)
+    for (int rb = g; rb < nr; rb += NG * kHpUnroll) {
+      E op[kHpUnroll], oj[kHpUnroll], oc[kHpUnroll];
+#pragma unroll
+      for (int u = 0; u < kHpUnroll; ++u) {
+        const E *row = Pl + min(rb + NG * u, nr - 1) * NB;
+        op[u] = upd ? row[p] : Num<E>::zero();
+        oj[u] = row[jc];
+        oc[u] = row[c < nbp ? c : 0];
+      }
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int u = 0; u < kHpUnroll; ++u) {
+        const int rl = rb + NG * u;
+        if (rl >= nr) break;
+        const int r = r0 + rl;
+        E *row = Pl + rl * NB;
+        E nc = oc[u], xj = oj[u];
+        if (upd && r >= p) {
+          const E v = r > p ? Num<E>::mul(op[u], sc) : Num<E>::real(1.0);
+          const E cv = Num<E>::mul(ct, v);
+          if (fact) xj = oj[u] - Num<E>::mul(cv, wj);
+          nc = (fact && c == j) ? xj : oc[u] - Num<E>::mul(cv, wc);
+          if (c == p && r > p) row[p] = v;
+          if (c > p && c < nbp) row[c] = nc;
+        }
+        if (fact && c >= j && c < nbp) {
+          if (r > j) acc = acc + Num<E>::mul(Num<E>::cj(xj), nc);
+          if (r == j) s_row[c] = nc;
+        }
+      }
+    }
+    if (!fact) break;
+    s_red[g][c] = acc;
+    __syncthreads();
+    E *partc = (E *)(hs + kHpPart) + (size_t)(j & 1) * kHpMaxBlocks * NB;
+    E *rowj = (E *)(hs + kHpRow) + (j & 1) * NB;
+    if (t < NB) {
+      E v = s_red[0][t];
+      for (int q = 1; q < NG; ++q) v = v + s_red[q][t];
+      hp_put(&partc[(size_t)blockIdx.x * NB + t], v);
+      if (j >= r0 && j < r0 + nr && t >= j && t < nbp) hp_put(&rowj[t], s_row[t]);
+    }
+    hp_barrier(ctr, base + (unsigned)(G * (j + 1)), err, limit);
+    {  // all blocks' sums, block order (thread (g, c) takes blocks g, g + NG, ...),
+       // every load in flight at once
+      E x[kHpLoads];
+      const bool col = c >= j && c < nbp;
+#pragma unroll
+      for (int u = 0; u < kHpLoads; ++u) {
+        const int b = g + NG * u;
+        x[u] = (col && b < G) ? hp_get<E>(&partc[(size_t)b * NB + c]) : Num<E>::zero();
+      }
+      const E rv = (g == 0 && col) ? hp_get<E>(&rowj[c]) : Num<E>::zero();
+      E v = x[0];
+#pragma unroll
+      for (int u = 1; u < kHpLoads; ++u) v = v + x[u];
+      s_red[g][c] = v;
+      if (g == 0) s_row[c] = rv;
+    }
+    __syncthreads();
+    if (t == j) {  // the reflector's scalars
+      const E alpha = s_row[j];
+      E sj = s_red[0][j];
+      for (int q = 1; q < NG; ++q) sj = sj + s_red[q][j];
+      const double xn2 = Num<E>::re(sj);
+      E tv = Num<E>::zero(), scn = Num<E>::zero();
+      double beta = Num<E>::re(alpha);
+      if (xn2 != 0.0 || Num<E>::im(alpha) != 0.0) {
+        beta = -copysign(sqrt(Num<E>::abs2(alpha) + xn2), Num<E>::re(alpha));
+        tv = Num<E>::scale(Num<E>::real(beta) - alpha, 1.0 / beta);
+        scn = recip(alpha - Num<E>::real(beta));
+      }
+      s_ct = Num<E>::cj(tv);
+      s_sc = scn;
+      if (blockIdx.x == 0) tau[j] = tv;
+      if (j >= r0 && j < r0 + nr) Pl[(j - r0) * NB + j] = Num<E>::real(beta);
+    }
+    __syncthreads();
+    if (t > j && t < nbp) {
+      E sv = s_red[0][t];
+      for (int q = 1; q < NG; ++q) sv = sv + s_red[q][t];
+      s_w[t] = s_row[t] + Num<E>::mul(Num<E>::cj(s_sc), sv);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int idx = t; idx < nr * nbp; idx += NT) {
+    const int rl = idx % nr, cc = idx / nr;
+    const int64_t r = (int64_t)r0 + rl;
+    const E x = Pl[rl * NB + cc];
+    P[r + (int64_t)cc * ld] = x;
+    if (r >= cc) Vb[r + (int64_t)cc * ldv] = r > cc ? x : Num<E>::real(1.0);
+  }
+}
+
 // T (nb x nb, upper triangular) of the compact WY form H_0 ... H_{nb-1} =
 // I - V T V^H from S = V^H V and tau: T[i][i] = tau_i and
 // T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i].  One packed upper triangle in
@@ -914,6 +1119,62 @@ void hh_column(bool cplx, void *P, int64_t ld, int Mp, int nbp, int jj, void *Vb
   else
     hipLaunchKernelGGL((k_hh_column<double, kHhNB>), dim3(nblk), dim3(256), 0, s, (double *)P, ld,
                        Mp, nbp, jj, nprev, (double *)Vb, ldv, (double *)tau, (char *)hh_state);
+}
+
+template <typename E>
+static bool hh_panel_launch(E *P, int64_t ld, int Mp, int nbp, E *Vb, int64_t ldv, E *tau,
+                            char *hs, unsigned *base, hipStream_t s) {
+  struct Info { int ncu, per; long long ticks; };
+  auto kern = k_hh_panel<E, kHhNB, kHpGroups>;
+  // once per process (thread-safe static initialisation)
+  static const Info info = [&] {
+    const size_t lds_max = (size_t)kHpMaxRows * kHhNB * sizeof(E);
+    Info f{0, 0, 0};
+    int dev = 0, khz = 0;
+    CHASE_HIP(hipGetDevice(&dev));
+    CHASE_HIP(hipDeviceGetAttribute(&f.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    CHASE_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    CHASE_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_max));
+    CHASE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.per, kern, kHpThreads, lds_max));
+    f.ticks = (long long)khz * 1000LL * 2;  // two seconds
+    return f;
+  }();
+  // about kHpRows rows per block, one block per compute unit at most
+  int G = std::max(1, std::min(info.ncu, (Mp + kHpRows - 1) / kHpRows));
+  int R = (Mp + G - 1) / G;
+  if (R > kHpMaxRows || G > kHpGroups * kHpLoads || info.per < 1) return false;
+  G = (Mp + R - 1) / R;
+  const size_t lds = (size_t)R * kHhNB * sizeof(E);
+  unsigned b0 = *base;
+  long long ticks = info.ticks;
+  void *args[] = {&P, &ld, &Mp, &nbp, &R, &Vb, &ldv, &tau, &hs, &b0, &ticks};
+  CHASE_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(G), dim3(kHpThreads), args, lds, s));
+  *base += (unsigned)(G * nbp);
+  return true;
+}
+
+bool hh_panel(bool cplx, void *P, int64_t ld, int Mp, int nbp, void *Vb, int64_t ldv, void *tau,
+              void *hh_state, unsigned *base, hipStream_t s) {
+  if (nbp < 1 || nbp > kHhNB || Mp < nbp) throw InvalidArg();
+  char *hs = (char *)hh_state + kHpBase;
+  if (cplx)
+    return hh_panel_launch<double2>((double2 *)P, ld, Mp, nbp, (double2 *)Vb, ldv, (double2 *)tau,
+                                    hs, base, s);
+  return hh_panel_launch<double>((double *)P, ld, Mp, nbp, (double *)Vb, ldv, (double *)tau, hs,
+                                 base, s);
+}
+
+void hh_panel_reset(void *hh_state, hipStream_t s) {
+  fill_zero(false, (char *)hh_state + kHpBase + kHpCtr, 1, 8, 1, s);  // the counter's 64 bytes
+}
+
+void hh_panel_clear_error(void *hh_state, hipStream_t s) {
+  fill_zero(false, (char *)hh_state + kHpBase + kHpCtr + 64, 1, 8, 1, s);
+}
+
+const void *hh_panel_error(const void *hh_state) {
+  return (const char *)hh_state + kHpBase + kHpCtr + 64;
 }
 
 void hh_larft(bool cplx, const void *S, int64_t lds, const void *tau, void *T, int64_t ldt,

@@ -116,13 +116,33 @@ void real_to_elem(bool cplx, const double *Z, int n, void *X, int64_t ldx, hipSt
 // Householder QR helpers (geqrf convention, panels of kHhNB columns).
 constexpr int kHhNB = 32;         // columns of one panel of column steps
 constexpr int kHhMaxOuter = 128;  // columns of one block reflector (T at most this wide)
-constexpr size_t kHhStateBytes = (size_t)320 << 10;  // pivot rows, block sums (two each)
+// hh_state: the column steps' pivot rows and block sums (two each), then the
+// panel kernel's pivot rows, barrier counter, error flag and block sums
+constexpr int kHpMaxBlocks = 512;  // blocks of one panel launch
+constexpr int kHpRows = 128;       // rows per block the panel launch aims at
+constexpr int kHpMaxRows = 256;    // rows per block it accepts (LDS: 256 x 32 x 16 bytes)
+constexpr size_t kHpStateBytes = (size_t)2 * 16 * kHhNB + 256 + 2 * (size_t)kHpMaxBlocks * kHhNB * 16;
+constexpr size_t kHhStateBytes = ((size_t)320 << 10) + kHpStateBytes;
 // One column step jj (0..nbp) of the panel P (Mp x nbp from its first
 // diagonal element); Vb receives the explicit reflector vectors, tau the
 // panel's tau entries.  Step jj + 1 reads what step jj left in hh_state, so
 // the steps of one panel run in order on one stream.
 void hh_column(bool cplx, void *P, int64_t ld, int Mp, int nbp, int jj, void *Vb, int64_t ldv,
                void *tau, void *hh_state, hipStream_t s);
+// The whole column-step sequence of one panel in one cooperative launch
+// (same results as steps 0..nbp of hh_column up to the order of the block
+// sums).  Returns false, launching nothing, when the panel has too many rows
+// for its blocks' LDS; *base is the barrier counter's value before the
+// launch and is advanced past it.  hh_panel_reset zeroes the counter
+// (before the first panel of a factorisation, base = 0).  hh_panel_error is
+// the device address of an int that a barrier wait sets when it times out
+// (every factorisation since is invalid); it stays set until
+// hh_panel_clear_error.
+bool hh_panel(bool cplx, void *P, int64_t ld, int Mp, int nbp, void *Vb, int64_t ldv, void *tau,
+              void *hh_state, unsigned *base, hipStream_t s);
+void hh_panel_reset(void *hh_state, hipStream_t s);
+void hh_panel_clear_error(void *hh_state, hipStream_t s);
+const void *hh_panel_error(const void *hh_state);
 // T (nb x nb, nb <= kHhMaxOuter) of the compact WY form from S = V^H V and tau.
 void hh_larft(bool cplx, const void *S, int64_t lds, const void *tau, void *T, int64_t ldt,
               int nb, hipStream_t s);

@@ -563,6 +563,10 @@ static void apply_block_reflector(Ctx &c, bool cplx, const void *V, int64_t ldv,
 #ifndef CHASE_HH_OUTER
 #define CHASE_HH_OUTER 128
 #endif
+// 1: a panel's column steps in one cooperative launch when its rows fit
+#ifndef CHASE_HH_PANEL
+#define CHASE_HH_PANEL 1
+#endif
 
 // Blocked Householder QR of X (N x L) in the geqrf convention, then the
 // explicit Q (the first L columns of H_0 ... H_{L-1}) in X, as orgqr/ungqr
@@ -587,6 +591,8 @@ static void householder(Ctx &c, bool cplx, void *X, void *V, int64_t ld, int64_t
   auto tstore = [&](int p) { return (char *)w.G + es * (size_t)p * nbo * nbo; };
   fill_zero(cplx, V, ld, (int)N, L, c.stream);
   fill_zero(false, w.flag, 1, 1, 1, c.stream);  // the Gram's skip flag
+  hh_panel_reset(w.hh, c.stream);
+  unsigned hp_base = 0;
   for (int p = 0; p < np; ++p) {
     const int j0 = p * nbo, nbop = std::min(nbo, L - j0);
     for (int jq = j0; jq < j0 + nbop; jq += nbi) {
@@ -594,8 +600,12 @@ static void householder(Ctx &c, bool cplx, void *X, void *V, int64_t ld, int64_t
       const int64_t Mq = N - jq;
       void *Vq = at(V, jq, jq);
       void *tq = (char *)w.tau + es * jq;
-      for (int jj = 0; jj <= nbq; ++jj)
-        hh_column(cplx, at(X, jq, jq), ld, (int)Mq, nbq, jj, Vq, ld, tq, w.hh, c.stream);
+      // the panel's column steps in one launch, or one launch per step when
+      // its rows do not fit the blocks' LDS
+      if (!CHASE_HH_PANEL ||
+          !hh_panel(cplx, at(X, jq, jq), ld, (int)Mq, nbq, Vq, ld, tq, w.hh, &hp_base, c.stream))
+        for (int jj = 0; jj <= nbq; ++jj)
+          hh_column(cplx, at(X, jq, jq), ld, (int)Mq, nbq, jj, Vq, ld, tq, w.hh, c.stream);
       const int rest = j0 + nbop - jq - nbq;
       if (rest > 0) {
         gram(c, cplx, Vq, ld, Mq, nbq, w.T, 0);  // S = V^H V
@@ -616,6 +626,10 @@ static void householder(Ctx &c, bool cplx, void *X, void *V, int64_t ld, int64_t
     apply_block_reflector(c, cplx, at(V, j0, j0), ld, N - j0, nbop, tstore(p), false,
                           at(X, j0, j0), ld, L - j0);
   }
+  // the panel launches' time-out flag (sticky on the device since the
+  // caller's hh_panel_clear_error), read after the caller's synchronisation
+  CHASE_HIP(hipMemcpyAsync(w.h_flag + 3, hh_panel_error(w.hh), 4, hipMemcpyDeviceToHost,
+                           c.stream));
   CHASE_HIP(hipGetLastError());
 }
 
@@ -891,6 +905,8 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
   hipStream_t s = c.stream;
   chase_info inf;
   std::memset(&inf, 0, sizeof(inf));
+  w.h_flag[3] = 0;
+  hh_panel_clear_error(w.hh, s);
 
   // spectral bounds (Alg. 1: lambda_1, lambda_l, upper bound of lambda_n)
   double gamma, alpha, beta;
@@ -1024,6 +1040,10 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
       t_qr += elapsed(c.ev[4], c.ev[2]);  // approximate: the redo's QR span
       t_rr += elapsed(c.ev[2], c.ev[3]);
       t_res += elapsed(c.ev[3], c.ev[4]);
+    }
+    if (w.h_flag[3] != 0) {
+      set_error("Householder QR: a panel launch's grid barrier timed out");
+      throw DeviceError();
     }
     if (w.h_flag[2] != 0) {
       set_error("Rayleigh-Ritz: the projected eigenproblem did not converge (info " +

@@ -38,7 +38,8 @@ struct Work {
   // pinned host mirrors
   double *h_theta = nullptr, *h_resid = nullptr, *h_ab = nullptr;
   double *h_aux = nullptr;  // [0] ||X||_F^2, [1] shift of the last shifted pass
-  int *h_flag = nullptr;    // [0..1] QR failure flag, [2] eigensolver info
+  int *h_flag = nullptr;    // [0..1] QR failure flag, [2] eigensolver info,
+                            // [3] Householder panel barrier time-out
   int *h_perm = nullptr;
 };
 

@@ -149,9 +149,12 @@ def test_qr_fallback_to_householder(P, gpu, cplx):
 
 HH_SHAPES = [
     # N, L, cplx: one column, two one-column panels, N == L, ragged panels,
-    # several row blocks of the column kernel, and a narrow first-row panel
+    # several row blocks of the panel kernel, 254 rows per block (near its
+    # LDS limit), and more rows than its 256 blocks hold (one launch per
+    # column step instead)
     (300, 1, False), (257, 2, True), (64, 64, False), (96, 96, True), (257, 33, True),
-    (1100, 97, False), (5000, 200, True), (70000, 40, False),
+    (1100, 97, False), (5000, 200, True), (65000, 40, True), (70000, 40, False),
+    (80000, 40, True),
 ]
 
 
