@@ -109,8 +109,11 @@ __device__ void ql_tridiag(double *d, double *e, double *Z, int ldz, int m, doub
         const double mu = d[hi] - em * em / (del + copysign(hypot(del, em), del));
         double x = d[lo] - mu, zb = e[lo];
         for (int k = lo; k < hi; ++k) {
-          const double r = hypot(x, zb);
-          const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? -zb / r : 0.0;
+          // the entries are of the order of the matrix norm: no scaling
+          // against overflow is needed, and one reciprocal serves c and s
+          const double r = sqrt(x * x + zb * zb);
+          const double ri = r > 0.0 ? 1.0 / r : 0.0;
+          const double c = r > 0.0 ? x * ri : 1.0, s = -zb * ri;
           if (k > lo) e[k - 1] = r;
           const double p = d[k], q = e[k], u = d[k + 1];
           d[k] = c * c * p - 2.0 * c * s * q + s * s * u;
@@ -510,31 +513,31 @@ __device__ __forceinline__ int dc_bound(int i, int n, int t) {
 
 // One leaf per block: QR iteration on the leaf's tridiagonal, eigenvalues
 // ascending to w[a..b), eigenvectors to the diagonal block of Z (ld n).
-__global__ __launch_bounds__(256) void k_dc_leaf(const double *d, const double *e, int n, int D,
-                                                 double *w, double *Z, int *info) {
+__global__ __launch_bounds__(64) void k_dc_leaf(const double *d, const double *e, int n, int D,
+                                                double *w, double *Z, int *info) {
   __shared__ double sZ[kDcLeaf * (kDcLeaf + 1)];
   __shared__ double sd[kDcLeaf], se[kDcLeaf], sc[kDcLeaf], ss[kDcLeaf];
   __shared__ int srank[kDcLeaf], ctl[4];
   const int t = threadIdx.x;
   const int a = dc_bound(blockIdx.x, n, D), b = dc_bound(blockIdx.x + 1, n, D), m = b - a;
   constexpr int LZ = kDcLeaf + 1;
-  for (int i = t; i < m; i += 256) {
+  for (int i = t; i < m; i += 64) {
     double v = d[a + i];
     if (i == 0 && a > 0) v -= fabs(e[a - 1]);
     if (i == m - 1 && b < n) v -= fabs(e[b - 1]);
     sd[i] = v;
     se[i] = i + 1 < m ? e[a + i] : 0.0;
   }
-  for (int idx = t; idx < m * LZ; idx += 256) sZ[idx] = (idx % LZ == idx / LZ) ? 1.0 : 0.0;
+  for (int idx = t; idx < m * LZ; idx += 64) sZ[idx] = (idx % LZ == idx / LZ) ? 1.0 : 0.0;
   __syncthreads();
   ql_tridiag(sd, se, sZ, LZ, m, sc, ss, ctl);
   rank_ascending(sd, m, srank);
   __syncthreads();
-  for (int idx = t; idx < m * m; idx += 256) {
+  for (int idx = t; idx < m * m; idx += 64) {
     const int r = idx % m, c = idx / m;
     Z[(a + r) + (int64_t)(a + srank[c]) * n] = sZ[r + c * LZ];
   }
-  for (int i = t; i < m; i += 256) w[a + srank[i]] = sd[i];
+  for (int i = t; i < m; i += 64) w[a + srank[i]] = sd[i];
   if (t == 0 && ctl[3]) info[0] = 1;
 }
 
@@ -950,7 +953,7 @@ int dc_depth(int n) {
 
 void dc_leaves(const double *d, const double *e, int n, int D, double *w, double *Z, int *info,
                hipStream_t s) {
-  hipLaunchKernelGGL(k_dc_leaf, dim3(1u << D), dim3(256), 0, s, d, e, n, D, w, Z, info);
+  hipLaunchKernelGGL(k_dc_leaf, dim3(1u << D), dim3(64), 0, s, d, e, n, D, w, Z, info);
 }
 
 void dc_merge_pre(const double *e, int n, int t, const double *w, double *Zc, double *Qg,

@@ -65,43 +65,46 @@ __global__ __launch_bounds__(256) void k_trace_shift(E *G, int64_t ldg, int n, d
 // One work-group factors the b x b (b <= 64) diagonal block of G at (p0, p0)
 // from its upper triangle (G = R^H R, right-looking), writes R and R^{-1}
 // (upper, zero below the diagonal) and reports a non-positive or non-finite
-// pivot through flag.  Thread (c, part) = (t / 4, t % 4) keeps the entries
-// of column c in rows part, part + 4, ... in registers.  Step j of the
+// pivot through flag.  Thread (c, part) = (t / 8, t % 8) keeps the entries
+// of column c in rows part, part + 8, ... in registers (eight per thread:
+// eight waves, two per SIMD, so the latency of one wave's FP64 chain hides
+// behind the other's).  Step j of the
 // factorisation: the owners publish row j (unscaled) in LDS, one barrier,
 // and every thread scales it by 1 / sqrt(pivot) on the fly and updates its
 // entries below row j.  The inverse runs bottom-up by rows,
 // X[i][c] = (delta_ic - sum_{q > i} R[i][q] X[q][c]) / R[i][i], each sum
-// split over the four threads of column c and combined by shuffles, with R
+// split over the eight threads of column c and combined by shuffles, with R
 // read from LDS and X kept in registers: no barrier per row.
+constexpr int kCholParts = 8, kCholRows = 64 / kCholParts, kCholThreads = 64 * kCholParts;
 template <typename E>
-__global__ __launch_bounds__(256) void k_chol_diag(const E *G, int64_t ldg, E *R, int64_t ldr,
+__global__ __launch_bounds__(kCholThreads) void k_chol_diag(const E *G, int64_t ldg, E *R, int64_t ldr,
                                                    E *Ri, int64_t ldi, int p0, int b, int *flag,
                                                    int pass, int inject) {
   __shared__ E sR[64][65];
   __shared__ E srow[2][64];
   if (flag[0] != 0) return;
-  const int t = threadIdx.x, c = t >> 2, part = t & 3;
+  const int t = threadIdx.x, c = t / kCholParts, part = t % kCholParts;
   if (inject) {
     if (t == 0) { flag[0] = p0 + 1; flag[1] = pass; }
     return;
   }
   const bool col = c < b;
   const int cc = min(c, b - 1);
-  E a[16];
+  E a[kCholRows];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {  // unconditional loads from inside the block, then masked
-    const int i = part + 4 * k;
+  for (int k = 0; k < kCholRows; ++k) {  // unconditional loads from inside the block, then masked
+    const int i = part + kCholParts * k;
     const E g = G[(int64_t)(p0 + cc) * ldg + p0 + min(i, b - 1)];
     a[k] = Num<E>::sel(col && i <= c, g, Num<E>::zero());
   }
 #pragma unroll 1
   for (int j = 0; j < b; ++j) {
     E *rowb = srow[j & 1];
-    if (part == (j & 3) && col) {
+    if (part == j % kCholParts && col) {
       E v = Num<E>::zero();
 #pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (k == (j >> 2)) v = a[k];
+      for (int k = 0; k < kCholRows; ++k)
+        if (k == j / kCholParts) v = a[k];
       rowb[c] = v;
     }
     __syncthreads();
@@ -112,51 +115,51 @@ __global__ __launch_bounds__(256) void k_chol_diag(const E *G, int64_t ldg, E *R
     }
     const double rj = sqrt(d), inv = 1.0 / rj;
     const E ujc = Num<E>::scale(rowb[cc], inv);
-    E rv[16];  // row j at this thread's rows, all reads issued together
+    E rv[kCholRows];  // row j at this thread's rows, all reads issued together
 #pragma unroll
-    for (int k = 0; k < 16; ++k) rv[k] = rowb[min(part + 4 * k, b - 1)];
+    for (int k = 0; k < kCholRows; ++k) rv[k] = rowb[min(part + kCholParts * k, b - 1)];
     const E own = Num<E>::sel(c > j, ujc, Num<E>::real(rj));  // the new entry in row j
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {  // selects, no branches
-      const int i = part + 4 * k;
+    for (int k = 0; k < kCholRows; ++k) {  // selects, no branches
+      const int i = part + kCholParts * k;
       const E upd = a[k] - Num<E>::mul(Num<E>::cj(Num<E>::scale(rv[k], inv)), ujc);
       const E keep = Num<E>::sel(i > j && i <= c && col, upd, a[k]);
       a[k] = Num<E>::sel(i == j && c >= j, own, keep);
     }
   }
 #pragma unroll
-  for (int k = 0; k < 16; ++k) sR[part + 4 * k][c] = a[k];
+  for (int k = 0; k < kCholRows; ++k) sR[part + kCholParts * k][c] = a[k];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int i = part + 4 * k;
+  for (int k = 0; k < kCholRows; ++k) {
+    const int i = part + kCholParts * k;
     if (col && i < b) R[(int64_t)(p0 + c) * ldr + p0 + i] = a[k];
   }
   __syncthreads();
-  E x[16];
+  E x[kCholRows];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) x[k] = Num<E>::zero();
+  for (int k = 0; k < kCholRows; ++k) x[k] = Num<E>::zero();
 #pragma unroll 1
   for (int i = b - 1; i >= 0; --i) {
-    E rv[16];
+    E rv[kCholRows];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) rv[k] = sR[i][part + 4 * k];
+    for (int k = 0; k < kCholRows; ++k) rv[k] = sR[i][part + kCholParts * k];
     E s = Num<E>::zero();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < kCholRows; ++k) {
       const E term = Num<E>::mul(rv[k], x[k]);
-      s = Num<E>::sel(part + 4 * k > i, s + term, s);
+      s = Num<E>::sel(part + kCholParts * k > i, s + term, s);
     }
-    s = Num<E>::add_xor(s, 1);
-    s = Num<E>::add_xor(s, 2);
+#pragma unroll
+    for (int m = 1; m < kCholParts; m <<= 1) s = Num<E>::add_xor(s, m);
     const double inv = 1.0 / Num<E>::re(sR[i][i]);
     const E v = Num<E>::sel(c == i, Num<E>::real(inv), Num<E>::scale(-s, inv));
-    const bool own = part == (i & 3) && col && c >= i;
+    const bool own = part == i % kCholParts && col && c >= i;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = Num<E>::sel(own && k == (i >> 2), v, x[k]);
+    for (int k = 0; k < kCholRows; ++k) x[k] = Num<E>::sel(own && k == i / kCholParts, v, x[k]);
   }
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int i = part + 4 * k;
+  for (int k = 0; k < kCholRows; ++k) {
+    const int i = part + kCholParts * k;
     if (col && i < b) Ri[(int64_t)(p0 + c) * ldi + p0 + i] = x[k];
   }
 }
@@ -382,66 +385,67 @@ __device__ __forceinline__ void block_sums(double (&acc)[D], double (*s_red)[64]
 // One Lanczos step after the product w = H v_j, for orders small enough that
 // one work-group per run can stream the run's whole basis (there the
 // solver's form with several wide launches per step is latency-bound):
-// alpha_j = Re(v_j^H w), two passes of
-// classical Gram-Schmidt against the run's basis v_0..v_j (h = V^H w, then
-// w -= V h), beta_j = ||w||, v_{j+1} = w / beta_j.  The same steps and the
-// same layout as the wide form: run r's basis vector i is column
-// i nv + r of LV; alpha at ab[j nv + r], beta at ab[(k + j) nv + r].
+// two passes of classical Gram-Schmidt against the run's basis v_0..v_j
+// (h = V^H w, then w -= V h; alpha_j = Re h_j of the first pass, i.e.
+// Re(v_j^H w) before any update), beta_j = ||w||, v_{j+1} = w / beta_j.
+// Sixteen waves: wave q forms the inner products with v_q, v_{q+16}, ...
+// over all N entries and reduces them by shuffles, so a pass needs one
+// work-group barrier; the update and the norm use every thread.  The same
+// layout as the wide form: run r's basis vector i is column i nv + r of LV;
+// alpha at ab[j nv + r], beta at ab[(k + j) nv + r].
+constexpr int kLzSmallThreads = 1024;
 template <typename E>
-__global__ __launch_bounds__(256) void k_lz_step_small(E *LV, int64_t ldv, int N, int j, int nv,
-                                                       E *W, int64_t ldw, double *ab, int k) {
-  constexpr int ES = sizeof(E) / sizeof(double), CH = 16, D = CH * ES;
-  __shared__ double s_red[4][64];
-  __shared__ double s_out[64];
-  __shared__ double sh[256];
+__device__ __forceinline__ E wave_sum64(E v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = Num<E>::add_xor(v, m);
+  return v;
+}
+
+template <typename E>
+__global__ __launch_bounds__(kLzSmallThreads) void k_lz_step_small(E *LV, int64_t ldv, int N, int j,
+                                                                   int nv, E *W, int64_t ldw,
+                                                                   double *ab, int k) {
+  constexpr int NW = kLzSmallThreads / 64;
   __shared__ E s_h[kLzSmallMaxBasis];
-  const int r = blockIdx.x, t = threadIdx.x;
+  __shared__ double s_n[NW];
+  const int r = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int nb = j + 1;
   E *w = W + (int64_t)r * ldw;
   auto vcol = [&](int i) { return LV + ((int64_t)i * nv + r) * ldv; };
-  {
-    const E *vj = vcol(j);
-    double s = 0.0;
-    for (int n = t; n < N; n += 256)
-      s += Num<E>::re(vj[n]) * Num<E>::re(w[n]) + Num<E>::im(vj[n]) * Num<E>::im(w[n]);
-    s = block_sum256(s, sh);
-    if (t == 0) ab[(int64_t)j * nv + r] = s;
-  }
   for (int pass = 0; pass < 2; ++pass) {
-    for (int i0 = 0; i0 < nb; i0 += CH) {
-      double acc[D];
-#pragma unroll
-      for (int u = 0; u < D; ++u) acc[u] = 0.0;
-      for (int n = t; n < N; n += 256) {
-        const E wn = w[n];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const E y = Num<E>::mul(Num<E>::cj(vcol(min(i0 + u, nb - 1))[n]), wn);
-          acc[ES * u] += Num<E>::re(y);
-          if constexpr (ES == 2) acc[ES * u + 1] += Num<E>::im(y);
-        }
+    for (int i = wave; i < nb; i += NW) {
+      const E *vi = vcol(i);
+      E a0 = Num<E>::zero(), a1 = Num<E>::zero();
+      int n = lane;
+      for (; n + 64 < N; n += 128) {
+        a0 = a0 + Num<E>::mul(Num<E>::cj(vi[n]), w[n]);
+        a1 = a1 + Num<E>::mul(Num<E>::cj(vi[n + 64]), w[n + 64]);
       }
-      block_sums<D>(acc, s_red, s_out);
-      if (t < CH && i0 + t < nb) {
-        if constexpr (ES == 2) s_h[i0 + t] = make_double2(s_out[2 * t], s_out[2 * t + 1]);
-        else s_h[i0 + t] = s_out[t];
-      }
-      __syncthreads();
+      if (n < N) a0 = a0 + Num<E>::mul(Num<E>::cj(vi[n]), w[n]);
+      const E sum = wave_sum64(a0 + a1);
+      if (lane == 0) s_h[i] = sum;
     }
-    for (int n = t; n < N; n += 256) {
+    __syncthreads();
+    if (pass == 0 && t == 0) ab[(int64_t)j * nv + r] = Num<E>::re(s_h[j]);
+    for (int n = t; n < N; n += kLzSmallThreads) {
       E x = w[n];
       for (int i = 0; i < nb; ++i) x = x - Num<E>::mul(vcol(i)[n], s_h[i]);
       w[n] = x;
     }
     __syncthreads();
   }
-  double s = 0.0;
-  for (int n = t; n < N; n += 256) s += Num<E>::abs2(w[n]);
-  s = sqrt(block_sum256(s, sh));
-  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  double sq = 0.0;
+  for (int n = t; n < N; n += kLzSmallThreads) sq += Num<E>::abs2(w[n]);
+  sq = wave_sum64(sq);
+  if (lane == 0) s_n[wave] = sq;
+  __syncthreads();
+  double tot = 0.0;
+  for (int q = 0; q < NW; ++q) tot += s_n[q];
+  const double beta = sqrt(tot);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
   E *vn = vcol(j + 1);
-  for (int n = t; n < N; n += 256) vn[n] = Num<E>::scale(w[n], inv);
-  if (t == 0) ab[(int64_t)(k + j) * nv + r] = s;
+  for (int n = t; n < N; n += kLzSmallThreads) vn[n] = Num<E>::scale(w[n], inv);
+  if (t == 0) ab[(int64_t)(k + j) * nv + r] = beta;
 }
 
 // out (rows x nv, leading dimension ldo) = sum over nsplit partials (each
@@ -931,11 +935,11 @@ void trace_shift(bool cplx, void *G, int64_t ldg, int n, double coef, int add_sh
 void chol_diag(bool cplx, void *G, int64_t ldg, void *R, int64_t ldr, void *Ri, int64_t ldi,
                int p0, int b, int *flag, int pass, int inject, hipStream_t s) {
   if (cplx)
-    hipLaunchKernelGGL(k_chol_diag<double2>, dim3(1), dim3(256), 0, s, (const double2 *)G, ldg,
-                       (double2 *)R, ldr, (double2 *)Ri, ldi, p0, b, flag, pass, inject);
+    hipLaunchKernelGGL(k_chol_diag<double2>, dim3(1), dim3(kCholThreads), 0, s, (const double2 *)G,
+                       ldg, (double2 *)R, ldr, (double2 *)Ri, ldi, p0, b, flag, pass, inject);
   else
-    hipLaunchKernelGGL(k_chol_diag<double>, dim3(1), dim3(256), 0, s, (const double *)G, ldg,
-                       (double *)R, ldr, (double *)Ri, ldi, p0, b, flag, pass, inject);
+    hipLaunchKernelGGL(k_chol_diag<double>, dim3(1), dim3(kCholThreads), 0, s, (const double *)G,
+                       ldg, (double *)R, ldr, (double *)Ri, ldi, p0, b, flag, pass, inject);
 }
 
 void fill_zero(bool cplx, void *A, int64_t lda, int rows, int cols, hipStream_t s) {
@@ -1095,11 +1099,11 @@ void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void 
   if (N < 1 || N > kLzSmallMaxN || j < 0 || j >= k || k + 1 > kLzSmallMaxBasis || nv < 1)
     throw InvalidArg();
   if (cplx)
-    hipLaunchKernelGGL(k_lz_step_small<double2>, dim3(nv), dim3(256), 0, s, (double2 *)LV, ldv, N,
-                       j, nv, (double2 *)W, ldw, ab, k);
+    hipLaunchKernelGGL(k_lz_step_small<double2>, dim3(nv), dim3(kLzSmallThreads), 0, s,
+                       (double2 *)LV, ldv, N, j, nv, (double2 *)W, ldw, ab, k);
   else
-    hipLaunchKernelGGL(k_lz_step_small<double>, dim3(nv), dim3(256), 0, s, (double *)LV, ldv, N, j,
-                       nv, (double *)W, ldw, ab, k);
+    hipLaunchKernelGGL(k_lz_step_small<double>, dim3(nv), dim3(kLzSmallThreads), 0, s,
+                       (double *)LV, ldv, N, j, nv, (double *)W, ldw, ab, k);
 }
 
 static unsigned hh_blocks(int Mp, int jj) {
