@@ -322,6 +322,16 @@ chase_status chase_lanczos_bounds(const double *alpha, const double *beta, int32
  * prev not ordered (prev[0] <= prev[1] < prev[2]). */
 chase_status chase_sequence_bounds(const double *prev, double delta, double *out);
 
+/* Test hook for the failure path of the Householder QR (the fallback of
+ * Alg. 3): the panel factorisation's blocks meet at a grid barrier whose
+ * wait gives up after a wall-clock limit (two seconds; the cooperative
+ * launch keeps every block resident, so a correct run never reaches it),
+ * after which the QR reports EDEVICE.  ticks > 0 sets that limit in ticks of
+ * the device's wall clock (hipDeviceAttributeWallClockRate), ticks <= 0
+ * restores the default; process-wide, takes effect at the next launch.
+ * Always CHASE_OK. */
+chase_status chase_set_panel_wait_limit(int64_t ticks);
+
 const char *chase_strerror(chase_status s);
 const char *chase_last_error(void);
 

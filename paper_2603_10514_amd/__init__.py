@@ -123,6 +123,7 @@ _sig("chase_lanczos", ctypes.c_int, [ctypes.c_int, _p, _i64, _i64, _p, _i32, _i3
                                      _dp, _p])
 _sig("chase_lanczos_bounds", ctypes.c_int, [_dp, _dp, _i32, _i32, _i64, _i32, _dp])
 _sig("chase_sequence_bounds", ctypes.c_int, [_dp, _d, _dp])
+_sig("chase_set_panel_wait_limit", ctypes.c_int, [_i64])
 _sig("chase_strerror", ctypes.c_char_p, [ctypes.c_int])
 _sig("chase_last_error", ctypes.c_char_p, [])
 
@@ -413,6 +414,12 @@ def chase_sequence_bounds(prev, delta):
     _check(lib.chase_sequence_bounds(p.ctypes.data_as(_dp), float(delta),
                                      out.ctypes.data_as(_dp)), "chase_sequence_bounds")
     return tuple(float(x) for x in out)
+
+
+def chase_set_panel_wait_limit(ticks):
+    """Test hook: wall-clock ticks a Householder panel launch's barrier wait
+    may take before the QR reports a device error (<= 0: the default)."""
+    _check(lib.chase_set_panel_wait_limit(int(ticks)), "chase_set_panel_wait_limit")
 
 
 # ------------------------------------------------------ async handles -----

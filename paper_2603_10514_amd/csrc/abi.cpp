@@ -430,6 +430,11 @@ chase_status chase_sequence_bounds(const double *prev, double delta, double *out
   return CHASE_OK;
 }
 
+chase_status chase_set_panel_wait_limit(int64_t ticks) {
+  hh_panel_set_wait_limit((long long)ticks);
+  return CHASE_OK;
+}
+
 const char *chase_strerror(chase_status s) {
   switch (s) {
     case CHASE_OK: return "ok";

@@ -1,6 +1,7 @@
 // gfx950 kernels of the solver other than the GEMM core, the GEMM
 // instantiations, and their launchers.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "gemm.hpp"
@@ -692,13 +693,14 @@ __device__ __forceinline__ void hp_barrier(unsigned *ctr, unsigned target, int *
     const long long t0 = wall_clock64();
     unsigned polls = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if ((++polls & 63) == 0) {  // now and then: another block's time-out, or ours
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-        if (wall_clock64() - t0 > limit) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+      if (wall_clock64() - t0 > limit) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
+      // now and then: another block's time-out
+      if ((++polls & 63) == 0 &&
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        break;
       __builtin_amdgcn_s_sleep(1);
     }
   }
@@ -1125,6 +1127,11 @@ void hh_column(bool cplx, void *P, int64_t ld, int Mp, int nbp, int jj, void *Vb
                        Mp, nbp, jj, nprev, (double *)Vb, ldv, (double *)tau, (char *)hh_state);
 }
 
+// Wall-clock ticks a panel launch's barrier wait may take before it gives
+// up; <= 0: two seconds.
+static std::atomic<long long> g_hp_wait_ticks{0};
+void hh_panel_set_wait_limit(long long ticks) { g_hp_wait_ticks.store(ticks); }
+
 template <typename E>
 static bool hh_panel_launch(E *P, int64_t ld, int Mp, int nbp, E *Vb, int64_t ldv, E *tau,
                             char *hs, unsigned *base, hipStream_t s) {
@@ -1151,7 +1158,8 @@ static bool hh_panel_launch(E *P, int64_t ld, int Mp, int nbp, E *Vb, int64_t ld
   G = (Mp + R - 1) / R;
   const size_t lds = (size_t)R * kHhNB * sizeof(E);
   unsigned b0 = *base;
-  long long ticks = info.ticks;
+  const long long set = g_hp_wait_ticks.load();
+  long long ticks = set > 0 ? set : info.ticks;
   void *args[] = {&P, &ld, &Mp, &nbp, &R, &Vb, &ldv, &tau, &hs, &b0, &ticks};
   CHASE_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(G), dim3(kHpThreads), args, lds, s));
   *base += (unsigned)(G * nbp);

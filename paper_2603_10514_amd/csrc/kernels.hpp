@@ -141,6 +141,9 @@ void hh_column(bool cplx, void *P, int64_t ld, int Mp, int nbp, int jj, void *Vb
 bool hh_panel(bool cplx, void *P, int64_t ld, int Mp, int nbp, void *Vb, int64_t ldv, void *tau,
               void *hh_state, unsigned *base, hipStream_t s);
 void hh_panel_reset(void *hh_state, hipStream_t s);
+// Limit of a panel launch's barrier wait in wall-clock ticks (<= 0: two
+// seconds); process-wide, for tests of the time-out path.
+void hh_panel_set_wait_limit(long long ticks);
 void hh_panel_clear_error(void *hh_state, hipStream_t s);
 const void *hh_panel_error(const void *hh_state);
 // T (nb x nb, nb <= kHhMaxOuter) of the compact WY form from S = V^H V and tau.

@@ -177,6 +177,29 @@ def test_householder_matches_lapack_convention(P, gpu, N, L, cplx):
     assert np.array_equal(to_host(Xd2), Q)
 
 
+def test_householder_panel_wait_timeout_is_reported(P, gpu):
+    """The failure path of the panel kernel's grid barrier, forced from the
+    host: with a one-tick limit the waits give up at once (every block still
+    finishes), the QR reports a device error instead of returning a wrong
+    Q, and with the limit restored the next factorisation is correct."""
+    N, L = 5000, 64  # 40 blocks per panel launch
+    print("householder wait time-out case", N, L, flush=True)
+    X = planted_block(N, L, 1e3, 33, True)
+    try:
+        P.chase_set_panel_wait_limit(1)
+        Xd = to_dev(X, gpu)
+        with pytest.raises(P.ChaseError) as exc:
+            P.chase_qr_factor(Xd, "householder")
+        assert "timed out" in str(exc.value)
+    finally:
+        P.chase_set_panel_wait_limit(0)
+    Xd = to_dev(X, gpu)
+    assert not P.chase_qr_factor(Xd, "householder")
+    Q = to_host(Xd)
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(L)) <= 100 * L * U64
+    assert col_rel_err(Q, oqr.householder_qr(X)) <= 100 * L * 1e3 * U64
+
+
 @pytest.mark.parametrize("cplx", [False, True])
 def test_householder_rank_deficient(P, gpu, cplx):
     """Zero and repeated columns: the reflector of a zero column is the
