@@ -103,7 +103,10 @@ typedef struct chase_opts {
   chase_qr qr_policy;        /* default AUTO (Alg. 3)                           */
   double est_hi, est_lo;     /* Alg. 3 thresholds, default 1e8 and 20           */
   int32_t have_bounds;       /* 1: use lambda_1, lambda_l, lambda_max below     */
-  double lambda_1, lambda_l, lambda_max; /* lambda_max must bound the spectrum   */
+  double lambda_1, lambda_l, lambda_max; /* lambda_max must bound the spectrum
+                                            (Sec. 1.2); a Ritz value above it
+                                            raises it by that value + twice its
+                                            residual + 1e-3 of the Ritz span  */
   int32_t warm_start;        /* 1: evecs holds the start block V0 on entry      */
   uint64_t seed;             /* random start block / Lanczos vector otherwise   */
   int32_t lanczos_steps;     /* steps per Lanczos run, default 40               */
@@ -143,7 +146,10 @@ typedef struct chase_info {
                                 split along K)                                 */
   int32_t filter_fp32_iters; /* iterations whose whole filter ran in FP32      */
   double t_total, t_filter, t_qr, t_rr, t_resid, t_lanczos; /* seconds          */
-  double lambda_1, lambda_l, lambda_max; /* bounds used by the first filter     */
+  double lambda_1, lambda_l, lambda_max; /* bounds used by the first filter;
+                              lambda_max is the upper bound at the end: raised
+                              when a Ritz value exceeded it (then it was no
+                              bound: Ritz values never exceed the spectrum)  */
   int64_t matvecs_fp32;      /* part of matvecs filtered in FP32 (all columns,
                                 or the buffer columns after the switch)       */
   double t_filter_fp32;      /* part of t_filter spent in FP32 filter steps     */

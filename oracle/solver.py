@@ -23,7 +23,11 @@ Readings of points the paper leaves open (each is listed in the design notes):
     normalisation at the lowest locked value the filtered columns shrink by
     (|rho_{k+1}|/|rho_1|)^m against the unit-norm locked ones and kappa_2
     grows to about |rho_1|^m;
-  * degrees: see ``degrees.py`` (a reading pinned by a property).
+  * degrees: see ``degrees.py`` (a reading pinned by a property);
+  * upper bound: Sec. 1.2 requires beta >= lambda_n.  Ritz values never
+    exceed lambda_n, so a Ritz value above beta proves the bound wrong; beta
+    is then moved past it (``upper_bound_check``).  With a valid bound this
+    never happens.
 """
 from dataclasses import dataclass, field
 
@@ -56,6 +60,18 @@ def step0(V0):
         return cholqr(V0, 2)
     except CholeskyFailure as exc:
         return householder_qr(exc.x)
+
+
+def upper_bound_check(theta, r, beta):
+    """beta, or, when the largest Ritz value theta[-1] exceeds it (then beta
+    is not an upper bound of the spectrum: a Ritz value is at most lambda_n),
+    theta[-1] + 2 r[-1] + 1e-3 (theta[-1] - theta[0]): an eigenvalue lies
+    within r[-1] of theta[-1], taken twice over, plus a margin that keeps the
+    damped interval from collapsing when r[-1] = 0."""
+    top = float(theta[-1])
+    if top > beta:
+        return top + 2.0 * float(r[-1]) + 1e-3 * (top - float(theta[0]))
+    return beta
 
 
 def chase_solve(H, nev, nex, deg=20, tol=1e-10, *, V0, bounds=None,
@@ -134,6 +150,7 @@ def chase_solve(H, nev, nex, deg=20, tol=1e-10, *, V0, bounds=None,
         lam1 = lam[0] if k > 0 else float(theta[0])
         gamma = float(theta_act[0])
         alpha = float(theta[-1])
+        beta = upper_bound_check(theta, r, beta)
         c = 0.5 * (alpha + beta)
         e = 0.5 * (beta - alpha)
         if deg_opt:

@@ -1090,6 +1090,15 @@ chase_status solve(Ctx &c, const chase_opts &o, const void *H, int64_t N, int64_
     lam1 = k > 0 ? lam[0] : th[0];
     gamma = theta_act[0];
     alpha = th.back();
+    // beta must bound the spectrum (Sec. 1.2).  A Ritz value never exceeds
+    // lambda_n, so one above beta proves the bound wrong: move beta past it
+    // by twice its residual (an eigenvalue lies within one residual of it)
+    // plus a margin that keeps the damped interval open.  Inert whenever
+    // beta is a true bound.
+    if (th.back() > beta) {
+      beta = th.back() + 2.0 * rr.back() + 1e-3 * (th.back() - th.front());
+      inf.lambda_max = beta;
+    }
     const double c2 = 0.5 * (alpha + beta), e2 = 0.5 * (beta - alpha);
     m.assign(L - k, degree);
     if (o.deg_opt)

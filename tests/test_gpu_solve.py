@@ -60,6 +60,34 @@ def test_config_small_real_matches_oracle(P, gpu):
     assert np.max(np.linalg.norm(R, axis=0)) < 1e-10
 
 
+@pytest.mark.parametrize("beta", [0.5, 0.0])
+def test_wrong_upper_bound_raised_like_oracle(P, gpu, beta):
+    """An upper bound inside the spectrum (Sec. 1.2 requires beta >= lambda_n):
+    the library, like the oracle, raises it once a Ritz value exceeds it,
+    converges to the planted eigenvalues with the oracle's iteration history,
+    and reports the raised bound in info.lambda_max."""
+    N, nev, nex = 300, 20, 10
+    H, lam = synth.planted_numpy(N, "uniform", 11)
+    V0 = synth.start_block(N, nev + nex, 12)
+    print("wrong upper bound case beta", beta, flush=True)
+    ref = osolver.chase_solve(H, nev, nex, 20, 1e-10, V0=V0, bounds=(-1.0, -0.8, beta))
+    out = P.chase_solve(to_dev(H, gpu), nev, nex, 20, 1e-10, evecs=to_dev(V0, gpu), warm_start=1,
+                        have_bounds=1, lambda_1=-1.0, lambda_l=-0.8, lambda_max=beta)
+    assert out["status"] == P.CHASE_OK and ref.converged == nev
+    assert np.max(np.abs(out["evals"] - lam[:nev])) <= 1e-12
+    assert np.max(np.abs(out["evals"] - ref.evals)) <= 1e-12
+    assert out["info"]["iters"] == ref.iters
+    assert [r["locked"] for r in out["log"]] == [r["locked"] for r in ref.log]
+    assert out["info"]["lambda_max"] > beta and all(r["e"] > 0 for r in out["log"])
+    # the raised bound holds twice the residual of the search space's top
+    # Ritz pair, which is far from converged (the wrong bound let the filter
+    # amplify the top of the spectrum by a large factor): the two sides agree
+    # on it only to a few digits
+    assert out["log"][0]["e"] == pytest.approx(ref.log[0]["e"], rel=1e-14)
+    for g, o in zip(out["log"][1:], ref.log[1:]):
+        assert g["e"] == pytest.approx(o["e"], rel=1e-3)
+
+
 def test_complex_dft_family_matches_oracle(P, gpu):
     N, nev, nex = 800, 40, 16
     H, lam = synth.planted_numpy(N, "dft", 2, True)

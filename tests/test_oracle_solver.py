@@ -89,6 +89,32 @@ def test_householder_vs_dynamic_same_convergence():
     assert np.max(np.abs(auto.evals - hh.evals)) < 1e-12
 
 
+def test_upper_bound_check_is_inert_for_a_true_bound():
+    theta = np.array([-1.0, -0.5, 0.2])
+    r = np.array([1e-3, 1e-2, 0.3])
+    assert solver.upper_bound_check(theta, r, 0.2) == 0.2  # equal: still a bound
+    assert solver.upper_bound_check(theta, r, 5.0) == 5.0
+    # above it: theta_max + 2 r_max + 1e-3 (theta_max - theta_min)
+    assert solver.upper_bound_check(theta, r, 0.1) == pytest.approx(0.2 + 0.6 + 1.2e-3, rel=1e-15)
+    assert solver.upper_bound_check(theta, np.zeros(3), 0.1) > 0.2  # r = 0: interval stays open
+
+
+@pytest.mark.parametrize("beta", [0.5, 0.0])
+def test_wrong_upper_bound_is_detected_and_raised(beta):
+    """Sec. 1.2 needs beta >= lambda_n.  Given a beta inside the spectrum,
+    the first Rayleigh-Ritz step shows a Ritz value above it (Ritz values
+    never exceed lambda_n), beta is raised, every later damped interval is
+    non-empty (e > 0), and the solve still finds the planted eigenvalues."""
+    N, nev, nex = 300, 20, 10
+    H, lam = synth.planted_numpy(N, "uniform", 11)
+    V0 = synth.start_block(N, nev + nex, 12)
+    res = solver.chase_solve(H, nev, nex, 20, 1e-10, V0=V0, bounds=(-1.0, -0.8, beta))
+    assert res.converged == nev
+    assert np.max(np.abs(res.evals - lam[:nev])) < 1e-12
+    assert all(x["e"] > 0 for x in res.log)
+    assert any(x["c"] + x["e"] > beta + 1e-9 for x in res.log[1:])
+
+
 def test_search_space_must_exceed_nev():
     H, lam = synth.planted_numpy(20, "uniform", 1)
     with pytest.raises(ValueError):
