@@ -187,6 +187,32 @@ def host_description():
     return model, blas
 
 
+def qr_timing(N=20000, L=1300, reps=3):
+    """The QR step alone on a block of the bench workload's shape: median
+    time of chase_qr_factor per variant after one warm-up (the entry point's
+    copies of the block in and out, 2 x 0.4 GB, included)."""
+    import torch
+    import paper_2603_10514_amd as P
+    import synth
+    dev = torch.device("cuda:0")
+    X0 = synth.start_block_torch(N, L, 7, True, dev)
+    res = {}
+    for variant in ["householder", "chol2", "shifted"]:
+        ts = []
+        for rep in range(reps + 1):
+            X = X0.T.contiguous().T.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.chase_qr_factor(X, variant)
+            torch.cuda.synchronize()
+            if rep:
+                ts.append(time.perf_counter() - t0)
+        res[variant] = float(np.median(ts)) * 1e3
+        log("qr %s %dx%d complex: %.2f ms" % (variant, N, L, res[variant]))
+    print(json.dumps({"qr_ms": res, "N": N, "L": L, "dtype": "complex128", "reps": reps}),
+          flush=True)
+
+
 def serving(args):
     import torch
     from paper_2603_10514_amd import serve
@@ -309,6 +335,9 @@ def main():
                     choices=["auto", "chol1", "chol2", "shifted", "householder"],
                     help="force one QR variant every iteration (Table 3 compares "
                          "Householder QR with the estimate-driven choice)")
+    ap.add_argument("--qr-timing", action="store_true",
+                    help="instead of a solve: time chase_qr_factor (Householder, CholeskyQR2, "
+                         "shifted CholeskyQR2) on a Gaussian 20000 x 1300 complex block")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -317,6 +346,9 @@ def main():
 
     if args.workload == "c5":
         serving(args)
+        return
+    if args.qr_timing:
+        qr_timing()
         return
 
     import torch
