@@ -130,8 +130,14 @@ def test_qr_variant_matches_oracle(P, gpu, variant, kappa, cplx):
     print("qr %s kappa %.0e cplx %d: Q diff %.2e = %.2f kappa u" % (
         variant, kappa, cplx, diff, diff / (kappa * U64)), flush=True)
     assert diff <= 10 * (amp + L) * U64
+    # span: X - Q Q^H X = (X - Q R) - Q (Q^H Q - I) R, so its relative size is
+    # the backward error (a few u) plus the loss of orthogonality; this is
+    # what still binds at kappa = 1e11, where the Q comparison above allows
+    # 0.1 (the variants' span is exact to rounding whatever kappa is)
     span = np.linalg.norm(X - Q @ (Q.conj().T @ X)) / np.linalg.norm(X)
-    assert span <= 1e-10
+    print("qr %s kappa %.0e cplx %d: span %.2e orth %.2e" % (variant, kappa, cplx, span, orth),
+          flush=True)
+    assert span <= orth + 10 * L * U64
 
 
 @pytest.mark.parametrize("cplx", [False, True])
