@@ -346,43 +346,6 @@ __global__ __launch_bounds__(256) void k_norm_scale_cols(const E *w, int64_t ldw
   if (threadIdx.x == 0) beta[blockIdx.x] = s;
 }
 
-// Block sums of D doubles per thread over 256 threads (D a power of two up
-// to 64), in a fixed order: a halving exchange leaves partial sum `lane` in
-// lane `lane` of each wave, then the four waves are added in wave order.
-// Returns with out[0..D) filled (LDS) and the block synchronised.
-template <int D, int M>
-__device__ __forceinline__ void fold_lanes(double (&acc)[D]) {
-  if constexpr (M >= D) {
-#pragma unroll
-    for (int i = 0; i < D; ++i) acc[i] += __shfl_xor(acc[i], M);
-    fold_lanes<D, M / 2>(acc);
-  }
-}
-template <int D, int H>
-__device__ __forceinline__ void halve_lanes(double (&acc)[D], int lane) {
-  if constexpr (H >= 1) {
-    const bool up = (lane & H) != 0;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const double send = up ? acc[i] : acc[i + H];
-      const double keep = up ? acc[i + H] : acc[i];
-      acc[i] = keep + __shfl_xor(send, H);
-    }
-    halve_lanes<D, H / 2>(acc, lane);
-  }
-}
-template <int D>
-__device__ __forceinline__ void block_sums(double (&acc)[D], double (*s_red)[64], double *out) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  fold_lanes<D, 32>(acc);
-  halve_lanes<D, D / 2>(acc, lane);
-  __syncthreads();
-  s_red[wave][lane] = acc[0];
-  __syncthreads();
-  if (t < D) out[t] = s_red[0][t] + s_red[1][t] + s_red[2][t] + s_red[3][t];
-  __syncthreads();
-}
-
 // One Lanczos step after the product w = H v_j, for orders small enough that
 // one work-group per run can stream the run's whole basis (there the
 // solver's form with several wide launches per step is latency-bound):
