@@ -81,69 +81,90 @@ __device__ __forceinline__ void reflector(E alpha, double xn2, E &tau, double &b
 }
 
 // ------------------------------------------ tridiagonal QR (small orders) --
+// v of lane k (k uniform across the wave).
+__device__ __forceinline__ double lane_val(double v, int k) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, k);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), k);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Eigenvalues and eigenvectors of the symmetric tridiagonal (d, e) of order
 // m <= 64 held in LDS, by implicit QR steps with the Wilkinson shift (Golub
-// & Van Loan, Sec. 8.3): thread 0 finds the active block and generates one
-// sweep's Givens rotations, then threads 0..m-1 apply them to their rows of
-// Z (Z <- Z G, ldz, initialised by the caller).  On return d holds the
-// (unsorted) eigenvalues; ctl[3] = 1 if the sweep limit was reached.
-__device__ void ql_tridiag(double *d, double *e, double *Z, int ldz, int m, double *sc,
-                           double *ss, int *ctl) {
+// & Van Loan, Sec. 8.3), in the first wave of the block: lane i keeps d[i]
+// and e[i] in registers, every lane runs the sweep's rotation chain (the
+// entries it needs come by lane reads with a uniform index), and lane t < m
+// applies each rotation to row t of Z (ldz, initialised by the caller) as
+// it is generated, carrying the rotated column in a register.  The
+// negligible off-diagonals and the active block come from a wave vote.  On
+// return d holds the (unsorted) eigenvalues; ctl[3] = 1 if the sweep limit
+// was reached.  Every thread of the block calls it (one barrier at the end).
+__device__ void ql_tridiag(double *d, double *e, double *Z, int ldz, int m, int *ctl) {
   const int t = threadIdx.x;
-  const int max_sweeps = 30 * m + 30;
-  if (t == 0) ctl[3] = 0;
-  for (int sweep = 0;; ++sweep) {
-    if (t == 0) {
-      for (int i = 0; i + 1 < m; ++i)
-        if (fabs(e[i]) <= kEps * (fabs(d[i]) + fabs(d[i + 1]))) e[i] = 0.0;
-      int hi = m - 1;
-      while (hi > 0 && e[hi - 1] == 0.0) --hi;
+  if (t < 64) {
+    const int lane = t;
+    const bool row = lane < m;
+    double dl = row ? d[lane] : 0.0;
+    double el = lane + 1 < m ? e[lane] : 0.0;
+    const int max_sweeps = 30 * m + 30;
+    int failed = 0;
+    for (int sweep = 0;; ++sweep) {
+      const double dn = __shfl_down(dl, 1);
+      if (lane + 1 < m && fabs(el) <= kEps * (fabs(dl) + fabs(dn))) el = 0.0;
+      const unsigned long long nz = __ballot(lane + 1 < m && el != 0.0);
+      // the trailing unreduced block is rows lo..hi
+      const int hi = nz ? 64 - __clzll((long long)nz) : 0;
       if (hi == 0 || sweep >= max_sweeps) {
-        ctl[0] = -1;
-        if (hi != 0) ctl[3] = 1;
-      } else {
-        int lo = hi - 1;
-        while (lo > 0 && e[lo - 1] != 0.0) --lo;
-        const double del = 0.5 * (d[hi - 1] - d[hi]);
-        const double em = e[hi - 1];
-        const double mu = d[hi] - em * em / (del + copysign(hypot(del, em), del));
-        double x = d[lo] - mu, zb = e[lo];
-        for (int k = lo; k < hi; ++k) {
-          // the entries are of the order of the matrix norm: no scaling
-          // against overflow is needed, and one reciprocal serves c and s
-          const double r = sqrt(x * x + zb * zb);
-          const double ri = r > 0.0 ? 1.0 / r : 0.0;
-          const double c = r > 0.0 ? x * ri : 1.0, s = -zb * ri;
-          if (k > lo) e[k - 1] = r;
-          const double p = d[k], q = e[k], u = d[k + 1];
-          d[k] = c * c * p - 2.0 * c * s * q + s * s * u;
-          d[k + 1] = s * s * p + 2.0 * c * s * q + c * c * u;
-          e[k] = c * s * (p - u) + (c * c - s * s) * q;
-          if (k + 1 < hi) {
-            zb = -s * e[k + 1];
-            e[k + 1] = c * e[k + 1];
-            x = e[k];
-          }
-          sc[k] = c;
-          ss[k] = s;
-        }
-        ctl[0] = lo;
-        ctl[1] = hi;
+        failed = hi != 0;
+        break;
       }
-    }
-    __syncthreads();
-    const int lo = ctl[0], hi = ctl[1];
-    if (lo < 0) break;
-    if (t < m) {
+      const unsigned long long split = ~nz & ((1ull << (hi - 1)) - 1);
+      const int lo = split ? 64 - __clzll((long long)split) : 0;
+      const double del = 0.5 * (lane_val(dl, hi - 1) - lane_val(dl, hi));
+      const double em = lane_val(el, hi - 1);
+      const double mu = lane_val(dl, hi) - em * em / (del + copysign(hypot(del, em), del));
+      // p, q: the current d[k], e[k] (already rotated by step k - 1)
+      double p = lane_val(dl, lo), q = lane_val(el, lo);
+      double x = p - mu, zb = q;
+      double zc = row ? Z[lane + lo * ldz] : 0.0;
       for (int k = lo; k < hi; ++k) {
-        const double c = sc[k], s = ss[k];
-        const double a = Z[t + k * ldz], b = Z[t + (k + 1) * ldz];
-        Z[t + k * ldz] = c * a - s * b;
-        Z[t + (k + 1) * ldz] = s * a + c * b;
+        const double u = lane_val(dl, k + 1);
+        const double en = k + 1 < hi ? lane_val(el, k + 1) : 0.0;
+        const double zn = row ? Z[lane + (k + 1) * ldz] : 0.0;
+        // the entries are of the order of the matrix norm: no scaling
+        // against overflow is needed, and one reciprocal serves c and s
+        const double r = sqrt(x * x + zb * zb);
+        const double ri = r > 0.0 ? 1.0 / r : 0.0;
+        const double c = r > 0.0 ? x * ri : 1.0, s = -zb * ri;
+        if (k > lo && lane == k - 1) el = r;
+        const double dk = c * c * p - 2.0 * c * s * q + s * s * u;
+        const double dk1 = s * s * p + 2.0 * c * s * q + c * c * u;
+        const double ek = c * s * (p - u) + (c * c - s * s) * q;
+        if (lane == k) {
+          dl = dk;
+          el = ek;
+        }
+        if (k + 1 < hi) {
+          zb = -s * en;
+          q = c * en;
+          x = ek;
+        }
+        p = dk1;
+        if (row) {
+          Z[lane + k * ldz] = c * zc - s * zn;
+          zc = s * zc + c * zn;
+        }
       }
+      if (lane == hi) dl = p;
+      if (row) Z[lane + hi * ldz] = zc;
     }
-    __syncthreads();
+    if (row) {
+      d[lane] = dl;
+      e[lane] = el;
+    }
+    if (lane == 0) ctl[3] = failed;
   }
+  __syncthreads();
 }
 
 // rank[i] = position of d[i] in ascending order (ties by index), i < m.
@@ -266,7 +287,7 @@ __global__ __launch_bounds__(256) void k_heev_small(E *A, int64_t lda, int n, do
   constexpr int MX = kEigSmallMax;
   __shared__ E sA[MX][MX + 1];  // sA[c][r] = A(r, c)
   __shared__ double sZ[MX * (MX + 1)];
-  __shared__ double sd[MX], se[MX], sc[MX], ss[MX];
+  __shared__ double sd[MX], se[MX];
   __shared__ E stau[MX], sp[MX], sw[MX];
   __shared__ int srank[MX], ctl[4];
   const int t = threadIdx.x;
@@ -280,7 +301,7 @@ __global__ __launch_bounds__(256) void k_heev_small(E *A, int64_t lda, int n, do
   __syncthreads();
   if (t < n) sZ[t + t * (MX + 1)] = 1.0;
   __syncthreads();
-  ql_tridiag(sd, se, sZ, MX + 1, n, sc, ss, ctl);
+  ql_tridiag(sd, se, sZ, MX + 1, n, ctl);
   rank_ascending(sd, n, srank);
   __syncthreads();
   backtransform_lds<E, MX>(
@@ -516,7 +537,7 @@ __device__ __forceinline__ int dc_bound(int i, int n, int t) {
 __global__ __launch_bounds__(64) void k_dc_leaf(const double *d, const double *e, int n, int D,
                                                 double *w, double *Z, int *info) {
   __shared__ double sZ[kDcLeaf * (kDcLeaf + 1)];
-  __shared__ double sd[kDcLeaf], se[kDcLeaf], sc[kDcLeaf], ss[kDcLeaf];
+  __shared__ double sd[kDcLeaf], se[kDcLeaf];
   __shared__ int srank[kDcLeaf], ctl[4];
   const int t = threadIdx.x;
   const int a = dc_bound(blockIdx.x, n, D), b = dc_bound(blockIdx.x + 1, n, D), m = b - a;
@@ -530,7 +551,7 @@ __global__ __launch_bounds__(64) void k_dc_leaf(const double *d, const double *e
   }
   for (int idx = t; idx < m * LZ; idx += 64) sZ[idx] = (idx % LZ == idx / LZ) ? 1.0 : 0.0;
   __syncthreads();
-  ql_tridiag(sd, se, sZ, LZ, m, sc, ss, ctl);
+  ql_tridiag(sd, se, sZ, LZ, m, ctl);
   rank_ascending(sd, m, srank);
   __syncthreads();
   for (int idx = t; idx < m * m; idx += 64) {
