@@ -72,10 +72,9 @@ __global__ __launch_bounds__(256) void k_trace_shift(E *G, int64_t ldg, int n, d
 // behind the other's).  Step j of the
 // factorisation: the owners publish row j (unscaled) in LDS, one barrier,
 // and every thread scales it by 1 / sqrt(pivot) on the fly and updates its
-// entries below row j.  The inverse runs bottom-up by rows,
-// X[i][c] = (delta_ic - sum_{q > i} R[i][q] X[q][c]) / R[i][i], each sum
-// split over the eight threads of column c and combined by shuffles, with R
-// read from LDS and X kept in registers: no barrier per row.
+// entries below row j.  The inverse is blocked by eight (as a blocked
+// triangular inverse): eight barriers for the diagonal blocks' back
+// substitutions, run side by side, and two per block row after them.
 constexpr int kCholParts = 8, kCholRows = 64 / kCholParts, kCholThreads = 64 * kCholParts;
 template <typename E>
 __global__ __launch_bounds__(kCholThreads) void k_chol_diag(const E *G, int64_t ldg, E *R, int64_t ldr,
@@ -83,6 +82,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_diag(const E *G, int64_t 
                                                    int pass, int inject) {
   __shared__ E sR[64][65];
   __shared__ E srow[2][64];
+  __shared__ E sT[8][8][8], sW[8][64];
   if (flag[0] != 0) return;
   const int t = threadIdx.x, c = t / kCholParts, part = t % kCholParts;
   if (inject) {
@@ -128,40 +128,66 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_diag(const E *G, int64_t 
       a[k] = Num<E>::sel(i == j && c >= j, own, keep);
     }
   }
+  // R to LDS: zero below the diagonal and in the padding past b, except a
+  // unit diagonal there, so that the padded block's inverse is
+  // diag(R^{-1}, I)
 #pragma unroll
-  for (int k = 0; k < kCholRows; ++k) sR[part + kCholParts * k][c] = a[k];
+  for (int k = 0; k < kCholRows; ++k) {
+    const int i = part + kCholParts * k;
+    sR[i][c] = Num<E>::sel(col, a[k], Num<E>::sel(i == c, Num<E>::real(1.0), Num<E>::zero()));
+  }
 #pragma unroll
   for (int k = 0; k < kCholRows; ++k) {
     const int i = part + kCholParts * k;
     if (col && i < b) R[(int64_t)(p0 + c) * ldr + p0 + i] = a[k];
   }
   __syncthreads();
-  E x[kCholRows];
-#pragma unroll
-  for (int k = 0; k < kCholRows; ++k) x[k] = Num<E>::zero();
+  // X = R^{-1} by blocks of eight.  The diagonal blocks T_q = R_qq^{-1}
+  // first, wave q for block q (lane 8 i + j holds entry (i, j)), by back
+  // substitution over the block's rows; they become X's diagonal blocks.
+  const int nblk = (b + 7) / 8;
+  {
+    const int q = t >> 6, i = (t & 63) >> 3, j = t & 7, g0 = 8 * q;
 #pragma unroll 1
-  for (int i = b - 1; i >= 0; --i) {
-    E rv[kCholRows];
-#pragma unroll
-    for (int k = 0; k < kCholRows; ++k) rv[k] = sR[i][part + kCholParts * k];
-    E s = Num<E>::zero();
-#pragma unroll
-    for (int k = 0; k < kCholRows; ++k) {
-      const E term = Num<E>::mul(rv[k], x[k]);
-      s = Num<E>::sel(part + kCholParts * k > i, s + term, s);
+    for (int ii = 7; ii >= 0; --ii) {
+      if (q < nblk && i == ii && j >= ii) {
+        E s = Num<E>::sel(j == ii, Num<E>::real(1.0), Num<E>::zero());
+        for (int m = ii + 1; m <= j; ++m) s = s - Num<E>::mul(sR[g0 + ii][g0 + m], sT[q][m][j]);
+        sT[q][ii][j] = Num<E>::scale(s, 1.0 / Num<E>::re(sR[g0 + ii][g0 + ii]));
+      }
+      __syncthreads();
     }
-#pragma unroll
-    for (int m = 1; m < kCholParts; m <<= 1) s = Num<E>::add_xor(s, m);
-    const double inv = 1.0 / Num<E>::re(sR[i][i]);
-    const E v = Num<E>::sel(c == i, Num<E>::real(inv), Num<E>::scale(-s, inv));
-    const bool own = part == i % kCholParts && col && c >= i;
-#pragma unroll
-    for (int k = 0; k < kCholRows; ++k) x[k] = Num<E>::sel(own && k == i / kCholParts, v, x[k]);
+    if (q < nblk) sR[g0 + i][g0 + j] = j >= i ? sT[q][i][j] : Num<E>::zero();
+  }
+  __syncthreads();
+  // then block rows p from the bottom: X_pr = -T_p sum_{p < s <= r} R_ps X_sr,
+  // i.e. W(i, c) = sum over k in [8 (p + 1), c] of R(8 p + i, k) X(k, c) (X
+  // is upper triangular) and X(8 p + i, c) = -sum_{m >= i} T_p(i, m) W(m, c);
+  // X overwrites R's block row p, which no later block row reads.
+  {
+    const int wi = t & 7, wc = t >> 3;  // 8 rows x 64 columns
+#pragma unroll 1
+    for (int p = nblk - 2; p >= 0; --p) {
+      const int r0 = 8 * p, c0 = r0 + 8, cx = c0 + wc;
+      const bool act = cx < 8 * nblk;
+      E w = Num<E>::zero();
+      if (act)
+        for (int k = c0; k <= cx; ++k) w = w + Num<E>::mul(sR[r0 + wi][k], sR[k][cx]);
+      sW[wi][wc] = w;
+      __syncthreads();
+      if (act) {
+        E x = Num<E>::zero();
+        for (int m = wi; m < 8; ++m) x = x + Num<E>::mul(sT[p][wi][m], sW[m][wc]);
+        sR[r0 + wi][cx] = -x;
+      }
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int k = 0; k < kCholRows; ++k) {
     const int i = part + kCholParts * k;
-    if (col && i < b) Ri[(int64_t)(p0 + c) * ldi + p0 + i] = x[k];
+    if (col && i < b)
+      Ri[(int64_t)(p0 + c) * ldi + p0 + i] = i <= c ? sR[i][c] : Num<E>::zero();
   }
 }
 
