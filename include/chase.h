@@ -328,11 +328,14 @@ chase_status chase_lanczos_bounds(const double *alpha, const double *beta, int32
  * prev not ordered (prev[0] <= prev[1] < prev[2]). */
 chase_status chase_sequence_bounds(const double *prev, double delta, double *out);
 
-/* Test hook for the failure path of the Householder QR (the fallback of
- * Alg. 3): the panel factorisation's blocks meet at a grid barrier whose
- * wait gives up after a wall-clock limit (two seconds; the cooperative
- * launch keeps every block resident, so a correct run never reaches it),
- * after which the QR reports EDEVICE.  ticks > 0 sets that limit in ticks of
+/* Test hook for the failure path of the library's grid barriers: the
+ * blocks of the Householder QR's panel factorisation (the fallback of
+ * Alg. 3) and of the one-launch Lanczos of small orders (the spectral
+ * bounds of Alg. 1) meet at grid barriers whose waits give up after a
+ * wall-clock limit (two seconds; the cooperative launch keeps every block
+ * resident, so a correct run never reaches it), after which the call
+ * (chase_qr_factor, chase_lanczos, chase_solve) reports EDEVICE.
+ * ticks > 0 sets that limit in ticks of
  * the device's wall clock (hipDeviceAttributeWallClockRate), ticks <= 0
  * restores the default; process-wide, takes effect at the next launch.
  * Always CHASE_OK. */

@@ -417,8 +417,9 @@ def chase_sequence_bounds(prev, delta):
 
 
 def chase_set_panel_wait_limit(ticks):
-    """Test hook: wall-clock ticks a Householder panel launch's barrier wait
-    may take before the QR reports a device error (<= 0: the default)."""
+    """Test hook: wall-clock ticks a grid-barrier wait (Householder panel,
+    one-launch Lanczos) may take before the call reports a device error
+    (<= 0: the default)."""
     _check(lib.chase_set_panel_wait_limit(int(ticks)), "chase_set_panel_wait_limit")
 
 

@@ -1116,7 +1116,7 @@ void hh_column(bool cplx, void *P, int64_t ld, int Mp, int nbp, int jj, void *Vb
                        Mp, nbp, jj, nprev, (double *)Vb, ldv, (double *)tau, (char *)hh_state);
 }
 
-// Wall-clock ticks a panel launch's barrier wait may take before it gives
+// Wall-clock ticks a grid-barrier wait (panel and Lanczos launches) may take before it gives
 // up; <= 0: two seconds.
 static std::atomic<long long> g_hp_wait_ticks{0};
 void hh_panel_set_wait_limit(long long ticks) { g_hp_wait_ticks.store(ticks); }
@@ -1176,6 +1176,266 @@ void hh_panel_clear_error(void *hh_state, hipStream_t s) {
 
 const void *hh_panel_error(const void *hh_state) {
   return (const char *)hh_state + kHpBase + kHpCtr + 64;
+}
+
+// ------------------------------------------ Lanczos in one launch (small N) --
+// The solver's nv Lanczos runs (full reorthogonalisation: classical
+// Gram-Schmidt twice against the run's own basis) for small orders, all k
+// steps in one cooperative launch.  Block b owns rows [b R, b R + R) of
+// every vector and keeps its rows of the basis in LDS.  Step j:
+//  * w = H v_j on the block's rows, v_j staged in LDS chunk by chunk (V0 for
+//    j = 0; else the other blocks' rows of w_j from the exchange buffer XV,
+//    scaled by 1 / beta_{j-1} exactly as each block scales its own rows);
+//  * two Gram-Schmidt passes h = V^H w, w -= V h, the inner products as
+//    block partial sums, a grid barrier, and every block adding all blocks'
+//    partials in block order (all blocks agree bit for bit);
+//  * the block's rows of w (unnormalised) go to XV with its partial sum of
+//    |w|^2; after the barrier every block forms beta_j and v_{j+1} = w /
+//    beta_j.
+// Three grid barriers per step.  Cross-block data moves by agent-coherent
+// stores and loads (as in the Householder panel kernel); the partial sums
+// use two areas of `part`, alternating barrier by barrier.  Output as the
+// per-step launches write it: alpha_j of run r at ab[j nv + r], beta_j at
+// ab[(k + j) nv + r].
+#ifndef CHASE_LZC_ROWS
+#define CHASE_LZC_ROWS 16
+#endif
+constexpr int kLzcThreads = 256;
+constexpr size_t kLzcMaxLds = 144 * 1024;
+constexpr size_t kLzcStageBytes = 32 * 1024;  // staged chunk of v_j
+
+// out[e] = sum_{g < G} pr[g slot + e] for e < nE, every block in the same
+// order: the blocks split into Q consecutive ranges per value (Q from nE
+// alone), each range added in block order by one thread with its loads
+// issued sixteen at a time, then the ranges in order.  sQ: max(kLzcThreads,
+// nE) elements.  Ends with a barrier of the block.
+template <typename E>
+__device__ void lzc_sum_partials(const E *pr, int nE, int G, size_t slot, E *sQ, E *out) {
+  const int t = threadIdx.x;
+  const int Q = max(1, min(G, kLzcThreads / nE));
+  for (int idx = t; idx < nE * Q; idx += kLzcThreads) {
+    const int e = idx % nE, q = idx / nE;
+    const int g0 = q * G / Q, g1 = (q + 1) * G / Q;
+    E s = Num<E>::zero();
+    for (int g = g0; g < g1; g += 16) {
+      E x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        x[u] = g + u < g1 ? hp_get<E>(pr + (size_t)(g + u) * slot + e) : Num<E>::zero();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s = s + x[u];
+    }
+    sQ[idx] = s;
+  }
+  __syncthreads();
+  for (int e = t; e < nE; e += kLzcThreads) {
+    E s = Num<E>::zero();
+    for (int q = 0; q < Q; ++q) s = s + sQ[q * nE + e];
+    out[e] = s;
+  }
+  __syncthreads();
+}
+
+template <typename E, int NV>
+__global__ __launch_bounds__(kLzcThreads) void k_lanczos_coop(
+    const E *__restrict__ H, int64_t ldh, int N, int k, int R, const E *__restrict__ V0, E *XV,
+    double *ab, E *part, char *hs, unsigned base, long long limit) {
+  typedef Num<E> X;
+  constexpr int CH = (int)(kLzcStageBytes / (NV * sizeof(E)));  // columns per staged chunk
+  extern __shared__ __align__(16) char lzc_lds[];
+  const int nQ = max(kLzcThreads, (k + 1) * NV);
+  E *sB = (E *)lzc_lds;                    // (k + 1) x NV x R: this block's rows of the basis
+  E *sW = sB + (size_t)(k + 1) * NV * R;   // NV x R: its rows of w
+  E *sRed = sW + (size_t)NV * R;           // kLzcThreads x NV: product partials
+  E *sH = sRed + (size_t)kLzcThreads * NV; // (k + 1) x NV: Gram-Schmidt coefficients
+  E *sQ = sH + (size_t)(k + 1) * NV;       // nQ: range sums of lzc_sum_partials
+  E *sV = sQ + nQ;                         // CH x NV: staged chunk of v_j
+  __shared__ double sInv[NV];
+  unsigned *ctr = (unsigned *)(hs + kHpCtr);
+  int *err = (int *)(hs + kHpCtr + 64);
+  const int t = threadIdx.x, G = gridDim.x, b = blockIdx.x;
+  const int r0 = b * R, nr = min(R, N - r0);
+  const int CG = kLzcThreads / R, row = t % R, cg = t / R;
+  const size_t slot = (size_t)(k + 1) * NV;  // one block's partial sums
+  unsigned nbar = 0;
+  auto put_area = [&]() { return part + (size_t)((nbar + 1) & 1) * G * slot + (size_t)b * slot; };
+  auto get_area = [&]() { return (const E *)(part + (size_t)(nbar & 1) * G * slot); };
+  auto sync_grid = [&]() {
+    ++nbar;
+    hp_barrier(ctr, base + nbar * (unsigned)G, err, limit);
+  };
+  for (int e = t; e < NV * R; e += kLzcThreads) {
+    const int rr = e % R, r = e / R;
+    sB[(size_t)r * R + rr] = rr < nr ? V0[(int64_t)r * N + r0 + rr] : X::zero();
+  }
+  for (int j = 0; j < k; ++j) {
+    const int nb = j + 1;
+    // w = H v_j on this block's rows: thread (row, cg) takes the columns cg,
+    // cg + CG, ... of each chunk, sixteen loads of H in flight; the column
+    // groups' sums are then added in order
+    E acc[NV];
+#pragma unroll
+    for (int r = 0; r < NV; ++r) acc[r] = X::zero();
+    const E *vj = j == 0 ? V0 : XV;
+    for (int c0 = 0; c0 < N; c0 += CH) {
+      const int nc = min(CH, N - c0);
+      __syncthreads();  // the previous chunk is consumed
+      for (int e0 = t; e0 < nc * NV; e0 += 16 * kLzcThreads) {
+        E x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = e0 + u * kLzcThreads;  // column c0 + e % nc of run e / nc
+          x[u] = e < nc * NV ? hp_get<E>(vj + (int64_t)(e / nc) * N + c0 + e % nc) : X::zero();
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = e0 + u * kLzcThreads;
+          if (e < nc * NV)
+            sV[(e % nc) * NV + e / nc] = j == 0 ? x[u] : X::scale(x[u], sInv[e / nc]);
+        }
+      }
+      __syncthreads();
+      if (row < nr) {
+        const E *hr = H + r0 + row + (int64_t)c0 * ldh;
+        for (int c = cg; c < nc; c += 16 * CG) {
+          E h[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            h[u] = c + u * CG < nc ? hr[(int64_t)(c + u * CG) * ldh] : X::zero();
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (c + u * CG < nc)
+#pragma unroll
+              for (int r = 0; r < NV; ++r)
+                acc[r] = acc[r] + X::mul(h[u], sV[(c + u * CG) * NV + r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NV; ++r) sRed[(size_t)t * NV + r] = acc[r];
+    __syncthreads();
+    for (int e = t; e < NV * R; e += kLzcThreads) {
+      const int rr = e % R, r = e / R;
+      E s = X::zero();
+      for (int q = 0; q < CG; ++q) s = s + sRed[(size_t)(q * R + rr) * NV + r];
+      sW[(size_t)r * R + rr] = s;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      // h_i = v_i^H w (i <= j): this block's rows, then every block's
+      E *pw = put_area();
+      for (int e = t; e < nb * NV; e += kLzcThreads) {
+        const E *bi = sB + (size_t)e * R;  // entry e = i NV + r: basis vector i of run r
+        const E *wr = sW + (size_t)(e % NV) * R;
+        E s = X::zero();
+        for (int rr = 0; rr < nr; ++rr) s = s + X::mul(X::cj(bi[rr]), wr[rr]);
+        hp_put(pw + e, s);
+      }
+      sync_grid();
+      lzc_sum_partials(get_area(), nb * NV, G, slot, sQ, sH);
+      if (pass == 0 && b == 0 && t < NV) ab[(int64_t)j * NV + t] = X::re(sH[(size_t)j * NV + t]);
+      // w -= sum_i v_i h_i
+      for (int e = t; e < NV * R; e += kLzcThreads) {
+        const int rr = e % R, r = e / R;
+        if (rr < nr) {
+          E x = sW[(size_t)r * R + rr];
+          for (int i = 0; i < nb; ++i)
+            x = x - X::mul(sB[((size_t)i * NV + r) * R + rr], sH[(size_t)i * NV + r]);
+          sW[(size_t)r * R + rr] = x;
+        }
+      }
+      __syncthreads();
+    }
+    // beta_j = ||w||: the rows of w and the partial |w|^2 go out together;
+    // every block forms beta_j and v_{j+1} = w / beta_j from them
+    E *pw = put_area();
+    if (t < NV) {
+      double sq = 0.0;
+      for (int rr = 0; rr < nr; ++rr) sq += X::abs2(sW[(size_t)t * R + rr]);
+      hp_put(pw + t, X::real(sq));
+    }
+    if (j + 1 < k)
+      for (int e = t; e < NV * R; e += kLzcThreads) {
+        const int rr = e % R, r = e / R;
+        if (rr < nr) hp_put(XV + (int64_t)r * N + r0 + rr, sW[(size_t)r * R + rr]);
+      }
+    sync_grid();
+    lzc_sum_partials(get_area(), NV, G, slot, sQ, sH);
+    if (t < NV) {
+      const double beta = sqrt(X::re(sH[t]));
+      sInv[t] = beta > 0.0 ? 1.0 / beta : 0.0;
+      if (b == 0) ab[(int64_t)(k + j) * NV + t] = beta;
+    }
+    __syncthreads();
+    for (int e = t; e < NV * R; e += kLzcThreads) {
+      const int rr = e % R, r = e / R;
+      sB[((size_t)(j + 1) * NV + r) * R + rr] =
+          rr < nr ? X::scale(sW[(size_t)r * R + rr], sInv[r]) : X::zero();
+    }
+  }
+}
+
+template <typename E, int NV>
+static bool lzc_launch(const E *H, int64_t ldh, int N, int k, const E *V0, E *XV, double *ab,
+                       E *part, size_t part_bytes, char *hs, hipStream_t s) {
+  struct Info { int ncu, per; long long ticks; };
+  auto kern = k_lanczos_coop<E, NV>;
+  static const Info info = [&] {
+    Info f{0, 0, 0};
+    int dev = 0, khz = 0;
+    CHASE_HIP(hipGetDevice(&dev));
+    CHASE_HIP(hipDeviceGetAttribute(&f.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    CHASE_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    CHASE_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kLzcMaxLds));
+    CHASE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&f.per, kern, kLzcThreads, kLzcMaxLds));
+    f.ticks = (long long)khz * 1000LL * 2;  // two seconds
+    return f;
+  }();
+  // rows per block: a power of two from CHASE_LZC_ROWS, one block per
+  // compute unit at most
+  int R = CHASE_LZC_ROWS;
+  while ((int64_t)R * info.ncu < N) R *= 2;
+  if (R > kLzcThreads || info.per < 1) return false;
+  const int G = (N + R - 1) / R;
+  const size_t nq = std::max<size_t>(kLzcThreads, (size_t)(k + 1) * NV);
+  const size_t lds = sizeof(E) * ((size_t)(k + 1) * NV * R + (size_t)NV * R +
+                                  (size_t)kLzcThreads * NV + (size_t)(k + 1) * NV + nq) +
+                     kLzcStageBytes;
+  if (lds > kLzcMaxLds || 2 * sizeof(E) * (size_t)G * (k + 1) * NV > part_bytes) return false;
+  const long long set = g_hp_wait_ticks.load();
+  long long ticks = set > 0 ? set : info.ticks;
+  unsigned b0 = 0;
+  int R_ = R;
+  void *args[] = {&H, &ldh, &N, &k, &R_, &V0, &XV, &ab, &part, &hs, &b0, &ticks};
+  CHASE_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(G), dim3(kLzcThreads), args, lds,
+                                       s));
+  return true;
+}
+
+template <typename E>
+static bool lzc_nv(const E *H, int64_t ldh, int N, int k, int nv, const E *V0, E *XV, double *ab,
+                   E *part, size_t part_bytes, char *hs, hipStream_t s) {
+  switch (nv) {
+#define LZC(n) \
+  case n: return lzc_launch<E, n>(H, ldh, N, k, V0, XV, ab, part, part_bytes, hs, s);
+    LZC(1) LZC(2) LZC(3) LZC(4) LZC(5) LZC(6) LZC(7) LZC(8)
+#undef LZC
+    default: return false;
+  }
+}
+
+bool lanczos_coop(bool cplx, const void *H, int64_t ldh, int N, int k, int nv, const void *V0,
+                  void *XV, double *ab, void *part, size_t part_bytes, void *hh_state,
+                  hipStream_t s) {
+  if (N < 1 || k < 1 || nv < 1) throw InvalidArg();
+  char *hs = (char *)hh_state + kHpBase;
+  hh_panel_reset(hh_state, s);
+  if (cplx)
+    return lzc_nv<double2>((const double2 *)H, ldh, N, k, nv, (const double2 *)V0, (double2 *)XV,
+                           ab, (double2 *)part, part_bytes, hs, s);
+  return lzc_nv<double>((const double *)H, ldh, N, k, nv, (const double *)V0, (double *)XV, ab,
+                        (double *)part, part_bytes, hs, s);
 }
 
 void hh_larft(bool cplx, const void *S, int64_t lds, const void *tau, void *T, int64_t ldt,

@@ -69,6 +69,17 @@ constexpr int kLzSmallMaxBasis = 128;
 void lz_step_small(bool cplx, void *LV, int64_t ldv, int N, int j, int nv, void *W, int64_t ldw,
                    double *ab, int k, hipStream_t s);
 
+// All k steps of the nv Lanczos runs in one cooperative launch for small
+// orders (layout and outputs as lz_step_small's; V0: the normalised start
+// vectors, LV's first nv columns; XV: N x nv exchange buffer; part: partial
+// sums, 2 x blocks x (k + 1) x nv elements).  Resets the grid-barrier
+// counter in hh_state; a barrier time-out sets its error flag.  Returns
+// false (nothing launched) when a block's share does not fit its LDS or
+// part is too small.
+bool lanczos_coop(bool cplx, const void *H, int64_t ldh, int N, int k, int nv, const void *V0,
+                  void *XV, double *ab, void *part, size_t part_bytes, void *hh_state,
+                  hipStream_t s);
+
 // Hermitian eigensolver of the Rayleigh-Ritz matrix (eig.hip).
 constexpr int kEigSmallMax = 64;  // LDS-resident reduction / back transform up to this order
 constexpr int kEigQrMax = 24;     // tridiagonal QR for the whole problem up to this order

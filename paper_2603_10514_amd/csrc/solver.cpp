@@ -813,6 +813,11 @@ void rayleigh_ritz(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, con
   CHASE_HIP(hipGetLastError());
 }
 
+// Small orders take the one-launch Lanczos (lanczos_coop) unless this is 0.
+#ifndef CHASE_LZ_COOP
+#define CHASE_LZ_COOP 1
+#endif
+
 // nvec independent Lanczos runs of k steps, each with full
 // reorthogonalisation against its own basis (classical Gram-Schmidt, twice),
 // advanced together so that every step streams H once for all of them.  The
@@ -834,10 +839,20 @@ void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const voi
   else
     randn(cplx, w.LW, N, (int)N, nv, seed, c.stream);
   norm_scale_cols(cplx, w.LW, N, (int)N, nv, w.LV, N, w.lz_ab + (size_t)k * nv, c.stream);
-  // small orders: the steps after the product in one launch (one work-group
-  // per run); otherwise several wide launches per step
+  // small orders: every step in one cooperative launch, else the steps
+  // after the product in one launch each (one work-group per run); larger
+  // orders: several wide launches per step
   const bool small = N <= kLzSmallMaxN && k + 1 <= kLzSmallMaxBasis;
-  for (int j = 0; j < k; ++j) {
+  bool coop = false;
+  if (small && CHASE_LZ_COOP) {
+    hh_panel_clear_error(w.hh, c.stream);
+    coop = lanczos_coop(cplx, H, ldh, (int)N, k, nv, w.LV, w.LW, w.lz_ab, w.SK, w.sk_bytes, w.hh,
+                        c.stream);
+    if (coop)
+      CHASE_HIP(hipMemcpyAsync(w.h_flag + 3, hh_panel_error(w.hh), 4, hipMemcpyDeviceToHost,
+                               c.stream));
+  }
+  for (int j = 0; j < k && !coop; ++j) {
     const int nb = (j + 1) * nv;  // basis vectors so far, all runs
     void *Vj = (char *)w.LV + es * (size_t)N * j * nv;
     gemv_block(cplx, H, ldh, (int)N, (int)N, Vj, N, nv, w.LW, N, w.SK, w.sk_bytes, c.stream);
@@ -871,6 +886,10 @@ void lanczos(Ctx &c, bool cplx, const void *H, int64_t ldh, int64_t N, const voi
   CHASE_HIP(hipMemcpyAsync(w.h_ab, w.lz_ab, 16 * (size_t)k * nv, hipMemcpyDeviceToHost,
                            c.stream));
   CHASE_HIP(hipStreamSynchronize(c.stream));
+  if (coop && w.h_flag[3] != 0) {
+    set_error("Lanczos: a grid barrier of the one-launch run timed out");
+    throw DeviceError();
+  }
   alpha.assign((size_t)k * nv, 0.0);
   beta.assign((size_t)k * nv, 0.0);
   for (int r = 0; r < nv; ++r)

@@ -447,3 +447,27 @@ def test_filter_remainder_split_shapes(P, gpu, N, ncols, cplx, maxdeg):
     cols = np.unique(np.linspace(0, ncols - 1, 12).astype(int))
     ref = ofilter.chebyshev_filter(H, V[:, cols], deg[cols], c, e, g)
     assert col_rel_err(out[:, cols], ref) <= 4.0 * maxdeg * N * U64
+
+
+def test_lanczos_wait_timeout_is_reported(P, gpu):
+    """The failure path of the one-launch Lanczos's grid barriers, forced
+    from the host: with a one-tick limit the waits give up at once (every
+    block still finishes its bounded steps), the call reports a device error
+    instead of returning wrong coefficients, and with the limit restored the
+    next run matches the oracle."""
+    N, nvec = 1000, 4  # one launch of 63 blocks
+    print("lanczos wait time-out case", N, nvec, flush=True)
+    H, lam = synth.planted_numpy(N, "dft", 15, False)
+    V0 = synth.lanczos_starts(N, nvec, 16, False)
+    try:
+        P.chase_set_panel_wait_limit(1)
+        with pytest.raises(P.ChaseError) as exc:
+            P.chase_lanczos(to_dev(H, gpu), to_dev(V0, gpu), 40, 60)
+        assert "timed out" in str(exc.value)
+    finally:
+        P.chase_set_panel_wait_limit(0)
+    a, b, _ = P.chase_lanczos(to_dev(H, gpu), to_dev(V0, gpu), 40, 60)
+    a_ref, b_ref = olanczos.lanczos_tridiag(H, V0[:, 0], 40)
+    scale = np.max(np.abs(lam))
+    assert np.max(np.abs(a[0] - a_ref)) <= 1e-9 * scale
+    assert np.max(np.abs(b[0] - b_ref)) <= 1e-9 * scale
