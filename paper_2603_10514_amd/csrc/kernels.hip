@@ -24,6 +24,22 @@ __device__ __forceinline__ double block_sum256(double v, double *sh) {
   return r;
 }
 
+// P[0] + P[stride] + ... + P[(n - 1) stride] added in this order, the loads
+// issued sixteen at a time (the split partial sums of a K-split product;
+// there can be a few hundred of them)
+template <typename E>
+__device__ __forceinline__ E sum_strided(const E *P, int n, int64_t stride) {
+  E s = Num<E>::zero();
+  for (int q = 0; q < n; q += 16) {
+    E x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = q + u < n ? P[(int64_t)(q + u) * stride] : Num<E>::zero();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s = s + x[u];
+  }
+  return s;
+}
+
 // -------------------------------------------------- Hermitian reduction --
 template <typename E>
 __global__ void k_reduce_herm(const E *P, int nsplit, int64_t sstride, int64_t ldp, int n, E *G,
@@ -31,12 +47,11 @@ __global__ void k_reduce_herm(const E *P, int nsplit, int64_t sstride, int64_t l
   const int i = blockIdx.x * 16 + threadIdx.x;
   const int j = blockIdx.y * 16 + threadIdx.y;
   if (i >= n || j >= n || i > j) return;
-  E s = Num<E>::zero(), t = Num<E>::zero();
-  for (int q = 0; q < nsplit; ++q) {
-    s = s + P[q * sstride + (int64_t)j * ldp + i];
-    if (average) t = t + P[q * sstride + (int64_t)i * ldp + j];
+  E s = sum_strided(P + (int64_t)j * ldp + i, nsplit, sstride);
+  if (average) {
+    const E t = sum_strided(P + (int64_t)i * ldp + j, nsplit, sstride);
+    s = Num<E>::scale(s + Num<E>::cj(t), 0.5);
   }
-  if (average) s = Num<E>::scale(s + Num<E>::cj(t), 0.5);
   if (i == j) s = Num<E>::real(Num<E>::re(s));
   G[(int64_t)j * ldg + i] = s;
   G[(int64_t)i * ldg + j] = Num<E>::cj(s);
@@ -448,10 +463,8 @@ __global__ void k_sum_splits_diag(const E *P, int nsplit, int64_t sstride, int64
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= rows) return;
   const int c = blockIdx.y;
-  E s = Num<E>::zero();
-  if (q % nv == c)
-    for (int p = 0; p < nsplit; ++p) s = s + P[p * sstride + (int64_t)c * ldp + q];
-  out[(int64_t)c * ldo + q] = s;
+  out[(int64_t)c * ldo + q] =
+      q % nv == c ? sum_strided(P + (int64_t)c * ldp + q, nsplit, sstride) : Num<E>::zero();
 }
 
 // ------------------------------------------------- Householder QR (HHQR) --
@@ -877,9 +890,7 @@ __global__ void k_sum_splits(const E *P, int nsplit, int64_t sstride, int64_t ld
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= rows) return;
   const int64_t c = blockIdx.y;
-  E s = Num<E>::zero();
-  for (int p = 0; p < nsplit; ++p) s = s + P[p * sstride + c * ldp + q];
-  out[c * ldo + q] = s;
+  out[c * ldo + q] = sum_strided(P + c * ldp + q, nsplit, sstride);
 }
 
 // A (rows x cols) = the first cols columns of the identity.

@@ -165,12 +165,17 @@ static inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 // blocks (<= 1024) x one 128 x 64 complex (or 128 x 128 real) FP64 tile.
 static const size_t kTailScratch = (size_t)80 << 20;
 
+// K splits of the products with few output tiles: about 1024 work-groups,
+// at least kSplitRows rows each, at most kMaxSplits splits (a product with
+// one output tile, such as the Gram of a 32-column panel, then spreads over
+// the whole chip instead of 32 work-groups).
+constexpr int kSplitRows = 128, kMaxSplits = 256;
 static int gram_splits(int64_t N, int L) {
   const int t = (L + 63) / 64;
   const int tiles = t * (t + 1) / 2;
   int s = (1024 + tiles - 1) / tiles;
-  const int smax = (int)std::max<int64_t>(1, N / 256);
-  s = std::min(std::min(s, smax), 32);
+  const int smax = (int)std::max<int64_t>(1, N / kSplitRows);
+  s = std::min(std::min(s, smax), kMaxSplits);
   return std::max(s, 1);
 }
 static int lz_splits(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(128, N / 512)); }
@@ -514,8 +519,8 @@ static void trsm(Ctx &c, bool cplx, const void *Xin, void *Xout, int64_t ld, int
 // Split count of a K-split product with `tiles` output tiles over K rows.
 static int ksplits(int64_t K, int tiles) {
   int s = (1024 + tiles - 1) / tiles;
-  s = std::min<int64_t>(s, std::max<int64_t>(1, K / 256));
-  return std::max(1, std::min(s, 32));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, K / kSplitRows));
+  return std::max(1, std::min(s, kMaxSplits));
 }
 
 // C (Mp x n) <- (I - V op(T) V^H) C with op(T) = T^H (trans) or T: the block
