@@ -846,40 +846,100 @@ __global__ __launch_bounds__(NB * NG) void k_hh_panel(E *__restrict__ P, int64_t
 
 // T (nb x nb, upper triangular) of the compact WY form H_0 ... H_{nb-1} =
 // I - V T V^H from S = V^H V and tau: T[i][i] = tau_i and
-// T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i].  One packed upper triangle in
-// LDS holds S, and column i of T replaces column i of S once computed
-// (column i of T reads only T's earlier columns and S's column i).  Eight
-// threads share row t's dot product (lanes 8t .. 8t+7 of the block, summed
-// by shuffles within the wave).
+// T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i] for blocks of eight columns (side
+// by side, eight steps), then pairs of neighbouring blocks joined level by
+// level: for the columns L = [a, a + h) and R = [a + h, a + 2h),
+// T[L, R] = -T[L, L] S[L, R] T[R, R] (the product of the two compact WY
+// forms), W = S[L, R] T[R, R] first (held where T[L, R] goes), then
+// -T[L, L] W.  T is a packed upper triangle in LDS, S is read from global
+// memory; 8 + 3 log2(nb / 8) barriers instead of one or two per column.
 constexpr int kLarftThreads = 8 * kHhMaxOuter;
+constexpr int kLarftLeaf = 8;
 template <typename E>
 __global__ __launch_bounds__(kLarftThreads) void k_hh_larft(const E *S, int64_t lds, const E *tau,
                                                             E *T, int64_t ldt, int nb) {
+  typedef Num<E> X;
   __shared__ E sh[kHhMaxOuter * (kHhMaxOuter + 1) / 2];  // (k, i), k <= i, at i (i + 1) / 2 + k
-  const int tid = threadIdx.x, t = tid >> 3, sub = tid & 7;
-  for (int idx = tid; idx < nb * nb; idx += kLarftThreads) {
-    const int r = idx % nb, c = idx / nb;
-    if (r <= c) sh[c * (c + 1) / 2 + r] = S[r + (int64_t)c * lds];
-  }
-  __syncthreads();
-  for (int i = 0; i < nb; ++i) {
-    E v = Num<E>::zero();
-    if (t < i) {
-      const E *si = sh + i * (i + 1) / 2;
-      for (int k = t + sub; k < i; k += 8) v = v + Num<E>::mul(sh[k * (k + 1) / 2 + t], si[k]);
+  const int tid = threadIdx.x;
+  auto at = [](int k, int i) { return i * (i + 1) / 2 + k; };
+  // blocks of eight columns: thread (q, t) of wave q forms T[8q + t, 8q + i]
+  {
+    const int q = tid >> 6, t = tid & 63, c0 = kLarftLeaf * q;
+    const bool act = t < kLarftLeaf && c0 < nb;
+    const int gt = c0 + t;
+#pragma unroll 1
+    for (int i = 0; i < kLarftLeaf; ++i) {
+      const int gi = c0 + i;
+      if (act && gi < nb && t <= i) {
+        E v;
+        if (t == i) {
+          v = tau[gi];
+        } else {
+          E acc = X::zero();
+          for (int k = t; k < i; ++k)
+            acc = acc + X::mul(sh[at(gt, c0 + k)], S[(c0 + k) + (int64_t)gi * lds]);
+          v = -X::mul(tau[gi], acc);
+        }
+        sh[at(gt, gi)] = v;
+      }
+      __syncthreads();
     }
-    v = Num<E>::add_xor(v, 1);
-    v = Num<E>::add_xor(v, 2);
-    v = Num<E>::add_xor(v, 4);
-    if (t < i) v = -Num<E>::mul(tau[i], v);
-    else if (t == i) v = tau[i];
+  }
+  for (int h = kLarftLeaf; h < nb; h *= 2) {
+    // pair p: L = [2hp, 2hp + h), R = [2hp + h, min(2hp + 2h, nb)); entry
+    // (r, c) of the h x h block T[L, R] (c within R's columns)
+    const int npairs = (nb + 2 * h - 1) / (2 * h);
+    const int per = h * h;
+    // W = S[L, R] T[R, R]
+    for (int idx = tid; idx < npairs * per; idx += kLarftThreads) {
+      const int p = idx / per, r = (idx % per) % h, c = (idx % per) / h;
+      const int a = 2 * h * p, gr = a + r, gc = a + h + c;
+      if (gc >= nb) continue;
+      E acc = X::zero();
+      for (int k0 = 0; k0 <= c; k0 += 8) {  // S's loads eight at a time
+        E sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          sv[u] = k0 + u <= c ? S[gr + (int64_t)(a + h + k0 + u) * lds] : X::zero();
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (k0 + u <= c) acc = acc + X::mul(sv[u], sh[at(a + h + k0 + u, gc)]);
+      }
+      sh[at(gr, gc)] = acc;
+    }
     __syncthreads();
-    if (t <= i && sub == 0) sh[i * (i + 1) / 2 + t] = v;
+    // T[L, R] = -T[L, L] W, formed in registers, then stored
+    constexpr int kMaxOut = kHhMaxOuter * kHhMaxOuter / 4 / kLarftThreads;  // h <= nb / 2
+    E out[kMaxOut > 0 ? kMaxOut : 1];
+#pragma unroll
+    for (int u = 0; u < (kMaxOut > 0 ? kMaxOut : 1); ++u) {
+      const int idx = tid + u * kLarftThreads;
+      out[u] = X::zero();
+      if (idx < npairs * per) {
+        const int p = idx / per, r = (idx % per) % h, c = (idx % per) / h;
+        const int a = 2 * h * p, gr = a + r, gc = a + h + c;
+        if (gc < nb) {
+          E acc = X::zero();
+          for (int k = r; k < h; ++k) acc = acc + X::mul(sh[at(gr, a + k)], sh[at(a + k, gc)]);
+          out[u] = -acc;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (kMaxOut > 0 ? kMaxOut : 1); ++u) {
+      const int idx = tid + u * kLarftThreads;
+      if (idx < npairs * per) {
+        const int p = idx / per, r = (idx % per) % h, c = (idx % per) / h;
+        const int a = 2 * h * p, gr = a + r, gc = a + h + c;
+        if (gc < nb) sh[at(gr, gc)] = out[u];
+      }
+    }
     __syncthreads();
   }
   for (int idx = tid; idx < nb * nb; idx += kLarftThreads) {
     const int r = idx % nb, c = idx / nb;
-    T[r + (int64_t)c * ldt] = r <= c ? sh[c * (c + 1) / 2 + r] : Num<E>::zero();
+    T[r + (int64_t)c * ldt] = r <= c ? sh[at(r, c)] : X::zero();
   }
 }
 
