@@ -79,103 +79,135 @@ __global__ __launch_bounds__(256) void k_trace_shift(E *G, int64_t ldg, int n, d
 
 // ------------------------------------------- Cholesky of a diagonal block --
 // One work-group factors the b x b (b <= 64) diagonal block of G at (p0, p0)
-// from its upper triangle (G = R^H R, right-looking), writes R and R^{-1}
-// (upper, zero below the diagonal) and reports a non-positive or non-finite
-// pivot through flag.  Thread (c, part) = (t / 8, t % 8) keeps the entries
-// of column c in rows part, part + 8, ... in registers (eight per thread:
-// eight waves, two per SIMD, so the latency of one wave's FP64 chain hides
-// behind the other's).  Step j of the
-// factorisation: the owners publish row j (unscaled) in LDS, one barrier,
-// and every thread scales it by 1 / sqrt(pivot) on the fly and updates its
-// entries below row j.  The inverse is blocked by eight (as a blocked
-// triangular inverse): eight barriers for the diagonal blocks' back
-// substitutions, run side by side, and two per block row after them.
-constexpr int kCholParts = 8, kCholRows = 64 / kCholParts, kCholThreads = 64 * kCholParts;
+// from its upper triangle (G = R^H R), writes R and R^{-1} (upper, zero
+// below the diagonal) and reports a non-positive or non-finite pivot
+// through flag.  The block sits in LDS, padded past b with a unit diagonal
+// (so the padded block's factor is diag(R, I)), and is factored by panels
+// of eight columns, right-looking: wave 0 factors the 8 x 8 diagonal block
+// in registers (lane 8 i + j holds entry (i, j); pivots and rows move by
+// lane shuffles, no barrier) together with its inverse T_pp; then
+// R_p,right = T_pp^H G_p,right for the panel's rows, and the trailing
+// block takes the rank-8 update.  Three barriers per panel.  R^{-1} is then
+// formed by block rows from the bottom, X_pr = -T_p sum_{p<s<=r} R_ps X_sr,
+// two barriers per block row, its diagonal blocks being the T_pp.
+constexpr int kCholThreads = 512;
+
+template <typename E> __device__ __forceinline__ E shfl_e(E v, int src);
+template <> __device__ __forceinline__ double shfl_e(double v, int src) { return __shfl(v, src); }
+template <> __device__ __forceinline__ double2 shfl_e(double2 v, int src) {
+  return make_double2(__shfl(v.x, src), __shfl(v.y, src));
+}
+
 template <typename E>
 __global__ __launch_bounds__(kCholThreads) void k_chol_diag(const E *G, int64_t ldg, E *R, int64_t ldr,
                                                    E *Ri, int64_t ldi, int p0, int b, int *flag,
                                                    int pass, int inject) {
-  __shared__ E sR[64][65];
-  __shared__ E srow[2][64];
+  typedef Num<E> X;
+  __shared__ E sR[64][65];  // sR[i][c] = entry (i, c): the block, then R, then R^{-1}
   __shared__ E sT[8][8][8], sW[8][64];
+  __shared__ int s_fail;
   if (flag[0] != 0) return;
-  const int t = threadIdx.x, c = t / kCholParts, part = t % kCholParts;
+  const int t = threadIdx.x;
   if (inject) {
     if (t == 0) { flag[0] = p0 + 1; flag[1] = pass; }
     return;
   }
-  const bool col = c < b;
-  const int cc = min(c, b - 1);
-  E a[kCholRows];
-#pragma unroll
-  for (int k = 0; k < kCholRows; ++k) {  // unconditional loads from inside the block, then masked
-    const int i = part + kCholParts * k;
-    const E g = G[(int64_t)(p0 + cc) * ldg + p0 + min(i, b - 1)];
-    a[k] = Num<E>::sel(col && i <= c, g, Num<E>::zero());
+  for (int idx = t; idx < 64 * 64; idx += kCholThreads) {
+    const int i = idx & 63, c = idx >> 6;
+    E v = X::zero();
+    if (c < b) {
+      if (i <= c) v = G[(int64_t)(p0 + c) * ldg + p0 + i];
+    } else if (i == c) {
+      v = X::real(1.0);
+    }
+    sR[i][c] = v;
   }
+  if (t == 0) s_fail = 0;
+  __syncthreads();
+  const int nblk = (b + 7) / 8;
 #pragma unroll 1
-  for (int j = 0; j < b; ++j) {
-    E *rowb = srow[j & 1];
-    if (part == j % kCholParts && col) {
-      E v = Num<E>::zero();
+  for (int p = 0; p < nblk; ++p) {
+    const int g0 = 8 * p, g1 = g0 + 8, ncol = 8 * nblk - g1;
+    if (t < 64) {  // wave 0: R_pp and T_pp = R_pp^{-1}, lane 8 i + j
+      const int i = t >> 3, j = t & 7;
+      E a = j >= i ? sR[g0 + i][g0 + j] : X::zero();
+      double dinv_i = 0.0;
+      int fail = 0;
 #pragma unroll
-      for (int k = 0; k < kCholRows; ++k)
-        if (k == j / kCholParts) v = a[k];
-      rowb[c] = v;
+      for (int q = 0; q < 8; ++q) {
+        const double piv = X::re(shfl_e(a, 9 * q));
+        const E aqj = shfl_e(a, 8 * q + j), aqi = shfl_e(a, 8 * q + i);
+        if (fail == 0 && (!(piv > 0.0) || !isfinite(piv))) fail = q + 1;
+        if (fail == 0) {
+          const double rq = sqrt(piv), inv = 1.0 / rq;
+          if (i == q) dinv_i = inv;
+          const E rqj = X::scale(aqj, inv), rqi = X::scale(aqi, inv);
+          if (i == q)
+            a = j == q ? X::real(rq) : (j > q ? rqj : X::zero());
+          else if (i > q && j >= i)
+            a = a - X::mul(X::cj(rqi), rqj);
+        }
+      }
+      if (fail != 0) {
+        if (t == 0) s_fail = g0 + fail;
+      } else {
+        // column j of T_pp by back substitution: T(q, j) = (delta_qj -
+        // sum_{m > q} R(q, m) T(m, j)) / R(q, q), the sums accumulated row
+        // by row as the T(q, j) become known
+        E acc = X::zero(), tv = X::zero();
+#pragma unroll
+        for (int q = 7; q >= 0; --q) {
+          const E cand = X::scale(X::sel(i == j, X::real(1.0), X::zero()) - acc, dinv_i);
+          const E tqj = shfl_e(cand, 8 * q + j);
+          const E riq = shfl_e(a, 8 * i + q);
+          if (i == q) tv = j >= q ? tqj : X::zero();
+          if (i < q) acc = acc + X::mul(riq, tqj);
+        }
+        sR[g0 + i][g0 + j] = j >= i ? a : X::zero();
+        sT[p][i][j] = tv;
+      }
     }
     __syncthreads();
-    const double d = Num<E>::re(rowb[j]);
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (t == 0) { flag[0] = p0 + j + 1; flag[1] = pass; }
+    if (s_fail != 0) {
+      if (t == 0) { flag[0] = p0 + s_fail; flag[1] = pass; }
       return;
     }
-    const double rj = sqrt(d), inv = 1.0 / rj;
-    const E ujc = Num<E>::scale(rowb[cc], inv);
-    E rv[kCholRows];  // row j at this thread's rows, all reads issued together
-#pragma unroll
-    for (int k = 0; k < kCholRows; ++k) rv[k] = rowb[min(part + kCholParts * k, b - 1)];
-    const E own = Num<E>::sel(c > j, ujc, Num<E>::real(rj));  // the new entry in row j
-#pragma unroll
-    for (int k = 0; k < kCholRows; ++k) {  // selects, no branches
-      const int i = part + kCholParts * k;
-      const E upd = a[k] - Num<E>::mul(Num<E>::cj(Num<E>::scale(rv[k], inv)), ujc);
-      const E keep = Num<E>::sel(i > j && i <= c && col, upd, a[k]);
-      a[k] = Num<E>::sel(i == j && c >= j, own, keep);
-    }
-  }
-  // R to LDS: zero below the diagonal and in the padding past b, except a
-  // unit diagonal there, so that the padded block's inverse is
-  // diag(R^{-1}, I)
-#pragma unroll
-  for (int k = 0; k < kCholRows; ++k) {
-    const int i = part + kCholParts * k;
-    sR[i][c] = Num<E>::sel(col, a[k], Num<E>::sel(i == c, Num<E>::real(1.0), Num<E>::zero()));
-  }
-#pragma unroll
-  for (int k = 0; k < kCholRows; ++k) {
-    const int i = part + kCholParts * k;
-    if (col && i < b) R[(int64_t)(p0 + c) * ldr + p0 + i] = a[k];
-  }
-  __syncthreads();
-  // X = R^{-1} by blocks of eight.  The diagonal blocks T_q = R_qq^{-1}
-  // first, wave q for block q (lane 8 i + j holds entry (i, j)), by back
-  // substitution over the block's rows; they become X's diagonal blocks.
-  const int nblk = (b + 7) / 8;
-  {
-    const int q = t >> 6, i = (t & 63) >> 3, j = t & 7, g0 = 8 * q;
-#pragma unroll 1
-    for (int ii = 7; ii >= 0; --ii) {
-      if (q < nblk && i == ii && j >= ii) {
-        E s = Num<E>::sel(j == ii, Num<E>::real(1.0), Num<E>::zero());
-        for (int m = ii + 1; m <= j; ++m) s = s - Num<E>::mul(sR[g0 + ii][g0 + m], sT[q][m][j]);
-        sT[q][ii][j] = Num<E>::scale(s, 1.0 / Num<E>::re(sR[g0 + ii][g0 + ii]));
+    // R_p,right = T_pp^H G_p,right: rows g0 .. g0 + 7, columns g1 .. 8 nblk
+    {
+      const int wi = t & 7, wc = t >> 3;
+      if (wc < ncol) {
+        E s = X::zero();
+        for (int m = 0; m <= wi; ++m) s = s + X::mul(X::cj(sT[p][m][wi]), sR[g0 + m][g1 + wc]);
+        sW[wi][wc] = s;
       }
-      __syncthreads();
     }
-    if (q < nblk) sR[g0 + i][g0 + j] = j >= i ? sT[q][i][j] : Num<E>::zero();
+    __syncthreads();
+    // trailing update G_right,right -= R_p,right^H R_p,right (upper), and
+    // R_p,right into R's rows
+    for (int idx = t; idx < ncol * ncol; idx += kCholThreads) {
+      const int r = idx % ncol, cc = idx / ncol;
+      if (r <= cc) {
+        E s = sR[g1 + r][g1 + cc];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) s = s - X::mul(X::cj(sW[m][r]), sW[m][cc]);
+        sR[g1 + r][g1 + cc] = s;
+      }
+    }
+    for (int idx = t; idx < 8 * ncol; idx += kCholThreads) sR[g0 + (idx & 7)][g1 + (idx >> 3)] = sW[idx & 7][idx >> 3];
+    __syncthreads();
+  }
+  // R out; X's diagonal blocks are the T_pp
+  for (int idx = t; idx < 64 * 64; idx += kCholThreads) {
+    const int i = idx & 63, c = idx >> 6;
+    if (i < b && c < b) R[(int64_t)(p0 + c) * ldr + p0 + i] = i <= c ? sR[i][c] : X::zero();
   }
   __syncthreads();
-  // then block rows p from the bottom: X_pr = -T_p sum_{p < s <= r} R_ps X_sr,
+  for (int idx = t; idx < 64 * nblk; idx += kCholThreads) {
+    const int q = idx >> 6, i = (idx & 63) >> 3, j = idx & 7;
+    sR[8 * q + i][8 * q + j] = j >= i ? sT[q][i][j] : X::zero();
+  }
+  __syncthreads();
+  // block rows p from the bottom: X_pr = -T_p sum_{p < s <= r} R_ps X_sr,
   // i.e. W(i, c) = sum over k in [8 (p + 1), c] of R(8 p + i, k) X(k, c) (X
   // is upper triangular) and X(8 p + i, c) = -sum_{m >= i} T_p(i, m) W(m, c);
   // X overwrites R's block row p, which no later block row reads.
@@ -185,24 +217,22 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_diag(const E *G, int64_t 
     for (int p = nblk - 2; p >= 0; --p) {
       const int r0 = 8 * p, c0 = r0 + 8, cx = c0 + wc;
       const bool act = cx < 8 * nblk;
-      E w = Num<E>::zero();
+      E w = X::zero();
       if (act)
-        for (int k = c0; k <= cx; ++k) w = w + Num<E>::mul(sR[r0 + wi][k], sR[k][cx]);
+        for (int k = c0; k <= cx; ++k) w = w + X::mul(sR[r0 + wi][k], sR[k][cx]);
       sW[wi][wc] = w;
       __syncthreads();
       if (act) {
-        E x = Num<E>::zero();
-        for (int m = wi; m < 8; ++m) x = x + Num<E>::mul(sT[p][wi][m], sW[m][wc]);
+        E x = X::zero();
+        for (int m = wi; m < 8; ++m) x = x + X::mul(sT[p][wi][m], sW[m][wc]);
         sR[r0 + wi][cx] = -x;
       }
       __syncthreads();
     }
   }
-#pragma unroll
-  for (int k = 0; k < kCholRows; ++k) {
-    const int i = part + kCholParts * k;
-    if (col && i < b)
-      Ri[(int64_t)(p0 + c) * ldi + p0 + i] = i <= c ? sR[i][c] : Num<E>::zero();
+  for (int idx = t; idx < 64 * 64; idx += kCholThreads) {
+    const int i = idx & 63, c = idx >> 6;
+    if (i < b && c < b) Ri[(int64_t)(p0 + c) * ldi + p0 + i] = i <= c ? sR[i][c] : X::zero();
   }
 }
 
