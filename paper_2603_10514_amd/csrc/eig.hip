@@ -686,10 +686,12 @@ __global__ __launch_bounds__(256) void k_dc_deflate(const double *w, const doubl
   if (th == 0) a.kcnt[s] = k;
 }
 
-// Root j of 1 / rho + sum_i zl_i^2 / (dl_i - lambda) = 0 by bisection in
-// the shifted variable tau = lambda - dl_o, o the nearer pole (so that the
-// differences dl_i - lambda = (dl_i - dl_o) - tau keep their relative
-// accuracy): one wave per root, four roots per block.
+// Root j of 1 / rho + sum_i zl_i^2 / (dl_i - lambda) = 0 in the shifted
+// variable tau = lambda - dl_o, o the nearer pole (so that the differences
+// dl_i - lambda = (dl_i - dl_o) - tau keep their relative accuracy), by
+// Newton steps safeguarded by bisection (a step that leaves the bracket is
+// replaced by its midpoint; the bracket shrinks with every evaluation):
+// one wave per root, four roots per block.
 __global__ __launch_bounds__(256) void k_dc_secular(const double *e, int n, int t, DcPtrs a) {
   __shared__ double sdl[kEigMaxN], szz[kEigMaxN];
   const int i = blockIdx.x;
@@ -724,17 +726,32 @@ __global__ __launch_bounds__(256) void k_dc_secular(const double *e, int n, int 
     for (int q = lane; q < k; q += 64) zz += szz[q];
     o = k - 1; lo = 0.0; hi = rho * wave_sum(zz);
   }
+  // f increases from -inf to +inf on the bracket: Newton steps that stay
+  // strictly inside the shrinking bracket, else the midpoint, until a step
+  // (or the bracket) is below 2 u of the iterate
   const double dlo = sdl[o];
+  double mdl = 0.5 * (lo + hi), tau = mdl;
   for (int it = 0; it < 200; ++it) {
-    const double mdl = 0.5 * (lo + hi);
-    if (mdl == lo || mdl == hi) break;
-    double f = 0.0;
-    for (int q = lane; q < k; q += 64) f += szz[q] / ((sdl[q] - dlo) - mdl);
+    double f = 0.0, fp = 0.0;
+    for (int q = lane; q < k; q += 64) {
+      const double r = szz[q] / ((sdl[q] - dlo) - mdl);
+      f += r;
+      fp += r / ((sdl[q] - dlo) - mdl);
+    }
     f = ir + wave_sum(f);
+    fp = wave_sum(fp);
+    tau = mdl;
+    if (f == 0.0) break;
     if (f > 0.0) hi = mdl; else lo = mdl;
-    if (hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) break;
+    double nx = mdl - f / fp;
+    if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+    const double tol = 2.0 * kEps * fmax(fabs(lo), fabs(hi));
+    if (fabs(nx - mdl) <= 2.0 * kEps * fabs(nx) || hi - lo <= tol || nx == lo || nx == hi) {
+      tau = nx;
+      break;
+    }
+    mdl = nx;
   }
-  double tau = 0.5 * (lo + hi);
   if (tau == 0.0) tau = (o == j) ? hi : lo;
   if (lane == 0) {
     a.org[s + j] = o;
