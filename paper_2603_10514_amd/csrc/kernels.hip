@@ -1298,9 +1298,7 @@ const void *hh_panel_error(const void *hh_state) {
 // use two areas of `part`, alternating barrier by barrier.  Output as the
 // per-step launches write it: alpha_j of run r at ab[j nv + r], beta_j at
 // ab[(k + j) nv + r].
-#ifndef CHASE_LZC_ROWS
-#define CHASE_LZC_ROWS 16
-#endif
+constexpr int kLzcRows = 16;  // least rows per block (32 and 64 measured slower)
 constexpr int kLzcThreads = 256;
 constexpr size_t kLzcMaxLds = 144 * 1024;
 constexpr size_t kLzcStageBytes = 32 * 1024;  // staged chunk of v_j
@@ -1493,9 +1491,9 @@ static bool lzc_launch(const E *H, int64_t ldh, int N, int k, const E *V0, E *XV
     f.ticks = (long long)khz * 1000LL * 2;  // two seconds
     return f;
   }();
-  // rows per block: a power of two from CHASE_LZC_ROWS, one block per
-  // compute unit at most
-  int R = CHASE_LZC_ROWS;
+  // rows per block: a power of two from kLzcRows, one block per compute
+  // unit at most
+  int R = kLzcRows;
   while ((int64_t)R * info.ncu < N) R *= 2;
   if (R > kLzcThreads || info.per < 1) return false;
   const int G = (N + R - 1) / R;
