@@ -179,15 +179,17 @@ __device__ __forceinline__ void rank_ascending(const double *d, int m, int *rank
 
 // ------------------------------------------- one work-group (LDS) pieces --
 // Householder reduction of the m x m Hermitian matrix in LDS (sA[c][r] =
-// A(r, c), m <= MX) to the tridiagonal (sd, se): step j forms the reflector
-// of column j below the diagonal (wave 0, lane = row), p = tau B v with four
-// threads per row, w = p + kappa v with kappa = -tau (p^H v) / 2, and the
-// update B - v w^H - w v^H.  The reflectors stay below the subdiagonal of
-// sA (unit entry stored), their tau in stau.
+// A(r, c), m <= MX <= 64) to the tridiagonal (sd, se): step j forms the
+// reflector of column j below the diagonal (wave 0, lane = row, the unit
+// entry stored with it), p = tau B v with four threads per row, then every
+// wave forms kappa = -tau (p^H v) / 2 itself (m <= 64: lane = row, the same
+// sum in every wave) and the update B - v w^H - w v^H takes w = p + kappa v
+// entry by entry: three barriers per step.  The reflectors stay below the
+// subdiagonal of sA (unit entry stored), their tau in stau.  256 threads.
 template <typename E, int MX>
-__device__ void tridiag_lds(E (*sA)[MX + 1], int m, double *sd, double *se, E *stau, E *sp,
-                            E *sw) {
+__device__ void tridiag_lds(E (*sA)[MX + 1], int m, double *sd, double *se, E *stau, E *sp) {
   typedef Num<E> X;
+  static_assert(MX <= 64, "one wave holds a column");
   const int t = threadIdx.x, lane = t & 63;
   for (int j = 0; j + 1 < m; ++j) {
     if (t < 64) {
@@ -198,14 +200,13 @@ __device__ void tridiag_lds(E (*sA)[MX + 1], int m, double *sd, double *se, E *s
       double beta;
       reflector<E>(sA[j][j + 1], xn2, tau, beta, scale);
       if (r >= j + 2 && r < m) sA[j][r] = X::mul(x, scale);
+      if (r == j + 1) sA[j][j + 1] = X::real(1.0);
       if (r == 0) {
         stau[j] = tau;
         se[j] = beta;
         sd[j] = X::re(sA[j][j]);
       }
     }
-    __syncthreads();
-    if (t < 64 && lane == j + 1) sA[j][j + 1] = X::real(1.0);
     __syncthreads();
     const E tj = stau[j];
     {
@@ -218,19 +219,18 @@ __device__ void tridiag_lds(E (*sA)[MX + 1], int m, double *sd, double *se, E *s
       if (q == 0 && r < MX) sp[r] = (r >= j + 1 && r < m) ? X::mul(tj, acc) : X::zero();
     }
     __syncthreads();
-    if (t < 64) {
-      const int r = lane;
-      const bool in = r >= j + 1 && r < m;
-      const E pv = in ? X::mul(X::cj(sp[r]), sA[j][r]) : X::zero();
+    E kap;
+    {
+      const bool in = lane >= j + 1 && lane < m;
+      const E pv = in ? X::mul(X::cj(sp[lane]), sA[j][lane]) : X::zero();
       const double sr = wave_sum(X::re(pv)), si = wave_sum(X::im(pv));
-      const E kap = X::scale(X::mul(tj, mk<E>(sr, si)), -0.5);
-      if (in) sw[r] = sp[r] + X::mul(kap, sA[j][r]);
+      kap = X::scale(X::mul(tj, mk<E>(sr, si)), -0.5);
     }
-    __syncthreads();
     const int mm = m - j - 1;
     for (int idx = t; idx < mm * mm; idx += 256) {
       const int r = j + 1 + idx % mm, c = j + 1 + idx / mm;
-      sA[c][r] = sA[c][r] - X::mul(sA[j][r], X::cj(sw[c])) - X::mul(sw[r], X::cj(sA[j][c]));
+      const E wr = sp[r] + X::mul(kap, sA[j][r]), wc = sp[c] + X::mul(kap, sA[j][c]);
+      sA[c][r] = sA[c][r] - X::mul(sA[j][r], X::cj(wc)) - X::mul(wr, X::cj(sA[j][c]));
     }
     __syncthreads();
   }
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_heev_small(E *A, int64_t lda, int n, do
   __shared__ E sA[MX][MX + 1];  // sA[c][r] = A(r, c)
   __shared__ double sZ[MX * (MX + 1)];
   __shared__ double sd[MX], se[MX];
-  __shared__ E stau[MX], sp[MX], sw[MX];
+  __shared__ E stau[MX], sp[MX];
   __shared__ int srank[MX], ctl[4];
   const int t = threadIdx.x;
   for (int idx = t; idx < n * n; idx += 256) {
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_heev_small(E *A, int64_t lda, int n, do
     sA[c][r] = A[r + (int64_t)c * lda];
   }
   __syncthreads();
-  tridiag_lds<E, MX>(sA, n, sd, se, stau, sp, sw);
+  tridiag_lds<E, MX>(sA, n, sd, se, stau, sp);
   for (int idx = t; idx < n * (MX + 1); idx += 256) sZ[idx] = 0.0;
   __syncthreads();
   if (t < n) sZ[t + t * (MX + 1)] = 1.0;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_hetrd_tail(const E *A, int64_t lda, int
   constexpr int MX = kEigSmallMax;
   __shared__ E sA[MX][MX + 1];
   __shared__ double sd[MX], se[MX];
-  __shared__ E stau[MX], sp[MX], sw[MX], svp[MX], swp[MX];
+  __shared__ E stau[MX], sp[MX], svp[MX], swp[MX];
   const int t = threadIdx.x, m = n - j0;
   if (j0 > 0 && t < 64) {  // w of the previous step (rows j0 .. n-1)
     const int r = t;
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_hetrd_tail(const E *A, int64_t lda, int
     sA[c][r] = a;
   }
   __syncthreads();
-  tridiag_lds<E, MX>(sA, m, sd, se, stau, sp, sw);
+  tridiag_lds<E, MX>(sA, m, sd, se, stau, sp);
   for (int i = t; i < m; i += 256) {
     d[j0 + i] = sd[i];
     if (i + 1 < m) {

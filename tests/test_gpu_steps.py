@@ -471,3 +471,19 @@ def test_lanczos_wait_timeout_is_reported(P, gpu):
     scale = np.max(np.abs(lam))
     assert np.max(np.abs(a[0] - a_ref)) <= 1e-9 * scale
     assert np.max(np.abs(b[0] - b_ref)) <= 1e-9 * scale
+
+
+def test_lanczos_long_runs_take_the_per_step_launches(P, gpu):
+    """Bases too large for one block's LDS (8 complex runs of 100 steps: 16
+    rows x 101 vectors x 8 runs) leave the one-launch form for one launch
+    per step; the coefficients must still match the oracle's runs."""
+    N, nvec, steps = 600, 8, 100
+    print("lanczos per-step case", N, nvec, steps, flush=True)
+    H, lam = synth.planted_numpy(N, "dft", 15, True)
+    V0 = synth.lanczos_starts(N, nvec, 16, True)
+    a, b, _ = P.chase_lanczos(to_dev(H, gpu), to_dev(V0, gpu), steps, 60)
+    scale = np.max(np.abs(lam))
+    for r in range(nvec):
+        a_ref, b_ref = olanczos.lanczos_tridiag(H, V0[:, r], steps)
+        assert np.max(np.abs(a[r] - a_ref)) <= 1e-9 * scale, r
+        assert np.max(np.abs(b[r] - b_ref)) <= 1e-9 * scale, r
