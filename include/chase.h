@@ -301,8 +301,11 @@ chase_status chase_residuals(chase_dtype dtype, const void *HV, int64_t ldhv, co
  *              sum over Ritz values <= x of N |e_1^T s_j|^2 first reaches l,
  *              clamped to [lambda_1 + 1e-3 w, upper - 1e-3 w], w = upper - lambda_1.
  * Work is enqueued on `stream` (NULL: the library's) and the call returns
- * after it has finished.  Errors: EINVAL for NULL pointers or invalid sizes;
- * EDEVICE / ENOMEM as for the other calls. */
+ * after it has finished.  Orders up to 4096 run every step in one
+ * cooperative launch whose blocks meet at grid barriers (waits limited in
+ * time: see chase_set_panel_wait_limit).  Errors: EINVAL for NULL pointers
+ * or invalid sizes; EDEVICE when a barrier wait timed out; EDEVICE / ENOMEM
+ * as for the other calls. */
 chase_status chase_lanczos(chase_dtype dtype, const void *H, int64_t N, int64_t ldh,
                            const void *V0, int32_t nvec, int32_t steps, int32_t nsearch,
                            double *alpha, double *beta, double *bounds, void *stream);
