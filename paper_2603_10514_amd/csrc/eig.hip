@@ -17,6 +17,7 @@
 namespace chase {
 
 constexpr double kEps = 2.220446049250313e-16;  // 2^-52
+constexpr double kRsqMin = 1e-290;  // rsqrt_refined's inputs stay above this
 
 __device__ __forceinline__ double2 make_e(double r, double i, double2 *) { return make_double2(r, i); }
 __device__ __forceinline__ double make_e(double r, double, double *) { return r; }
@@ -132,10 +133,19 @@ __device__ void ql_tridiag(double *d, double *e, double *Z, int ldz, int m, int 
         const double en = k + 1 < hi ? lane_val(el, k + 1) : 0.0;
         const double zn = row ? Z[lane + (k + 1) * ldz] : 0.0;
         // the entries are of the order of the matrix norm: no scaling
-        // against overflow is needed, and one reciprocal serves c and s
-        const double r = sqrt(x * x + zb * zb);
-        const double ri = r > 0.0 ? 1.0 / r : 0.0;
-        const double c = r > 0.0 ? x * ri : 1.0, s = -zb * ri;
+        // against overflow is needed, and one reciprocal square root serves
+        // r, c and s (the refined hardware one on the chain; the correctly
+        // rounded pair near the bottom of the exponent range)
+        const double r2 = x * x + zb * zb;
+        double ri = 0.0, r = 0.0;
+        if (r2 > kRsqMin) {
+          ri = rsqrt_refined(r2);
+          r = r2 * ri;
+        } else if (r2 > 0.0) {
+          r = sqrt(r2);
+          ri = 1.0 / r;
+        }
+        const double c = r2 > 0.0 ? x * ri : 1.0, s = -zb * ri;
         if (k > lo && lane == k - 1) el = r;
         const double dk = c * c * p - 2.0 * c * s * q + s * s * u;
         const double dk1 = s * s * p + 2.0 * c * s * q + c * c * u;

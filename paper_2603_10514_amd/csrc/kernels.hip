@@ -92,20 +92,6 @@ __global__ __launch_bounds__(256) void k_trace_shift(E *G, int64_t ldg, int n, d
 // two barriers per block row, its diagonal blocks being the T_pp.
 constexpr int kCholThreads = 512;
 
-// 1 / sqrt(d) for a positive normal d: the hardware estimate refined by two
-// Newton steps, y <- y + y (1 - d y^2) / 2 (to about an ulp), seven
-// dependent operations where the correctly rounded square root and the
-// division that follows it take about twenty
-__device__ __forceinline__ double rsqrt_refined(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const double r = __builtin_fma(-d * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, r, y);
-  }
-  return y;
-}
-
 template <typename E> __device__ __forceinline__ E shfl_e(E v, int src);
 template <> __device__ __forceinline__ double shfl_e(double v, int src) { return __shfl(v, src); }
 template <> __device__ __forceinline__ double2 shfl_e(double2 v, int src) {
