@@ -139,7 +139,16 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_diag(const E *G, int64_t 
         const E aqj = shfl_e(a, 8 * q + j), aqi = shfl_e(a, 8 * q + i);
         if (fail == 0 && (!(piv > 0.0) || !isfinite(piv))) fail = q + 1;
         if (fail == 0) {
-          const double inv = rsqrt_refined(piv), rq = piv * inv;
+          // the refined reciprocal square root unless the pivot is near
+          // underflow (uniform across the wave)
+          double inv, rq;
+          if (piv > 1e-290) {
+            inv = rsqrt_refined(piv);
+            rq = piv * inv;
+          } else {
+            rq = sqrt(piv);
+            inv = 1.0 / rq;
+          }
           if (i == q) dinv_i = inv;
           const E rqj = X::scale(aqj, inv), rqi = X::scale(aqi, inv);
           if (i == q)
